@@ -1,0 +1,141 @@
+/*
+ * qmc.h -- C ABI of the MI355X (gfx950) Slater-Jastrow VMC library.
+ *
+ * What the library computes (paper: "QMCTorch: Molecular Wavefunctions with
+ * Neural Components for Energy and Force Calculations"):
+ *   - the molecular Hamiltonian of the Introduction (eq. Hmol), atomic units;
+ *   - the Slater-Jastrow wavefunction Psi = exp(J) sum_n d_n D_n^up D_n^dn
+ *     of the Methods section (eq. psimol) without backflow, with Slater or
+ *     contracted Cartesian Gaussian AOs (AO layer), MOs phi = sum C chi (MO
+ *     layer, C = c * mu), and the e-e Pade Jastrow of eq. pade_kernel;
+ *   - the local energy E_L = H Psi / Psi with the kinetic split of the
+ *     appendix on local energies, the Jacobi-trace derivatives of
+ *     eq. claudia_trace and the excited-determinant update of eq. table;
+ *   - all-electron Metropolis sampling (appendix on optimisation parameters,
+ *     Sampling paragraph) whose Monte Carlo mean of E_L estimates the
+ *     variational energy (eq. Ev).
+ *
+ * Conventions.
+ *   - Electrons 0..n_up-1 are spin up, n_up..n_up+n_dn-1 spin down.
+ *   - Walker positions X are [W][N_e][3] doubles, row-major, bohr.
+ *   - Device pointers (prefix d_) are caller-owned device memory on the
+ *     system's device; the library never frees them.  Host pointers in the
+ *     descriptor are copied at create and may be freed afterwards.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *     call is asynchronous on that stream; results are valid once the stream
+ *     has been synchronised.
+ *   - One handle is used from one host thread at a time.
+ *   - No call aborts, throws or prints.  Argument checks run before any
+ *     launch and return QMC_EINVAL; an unsupported shape returns
+ *     QMC_EUNSUPPORTED; a HIP runtime failure returns QMC_EDEVICE.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QMC_OK = 0,
+    QMC_EINVAL = -1,        /* invalid argument or descriptor */
+    QMC_ENOMEM = -2,        /* device allocation failed */
+    QMC_EDEVICE = -3,       /* HIP runtime error (or no device) */
+    QMC_EUNSUPPORTED = -4   /* valid input outside the compiled limits */
+} qmc_status;
+
+/* Arithmetic of a call.  QMC_FP64: everything in FP64.  QMC_MIXED_FP32 and
+   QMC_MIXED_BF16: AO values and the AO->MO contraction in reduced precision
+   (FP32 arithmetic; BF16 operands with FP32 accumulation), determinants,
+   Jacobi traces, Jastrow and E_L in FP64. */
+typedef enum { QMC_FP64 = 0, QMC_MIXED_FP32 = 1, QMC_MIXED_BF16 = 2 } qmc_precision;
+
+/* Radial form of every AO: Slater r^kn exp(-zeta r) or contracted
+   Gaussians sum_p c_p exp(-alpha_p r^2) (Methods, AO layer). */
+typedef enum { QMC_STO = 0, QMC_GTO = 1 } qmc_basis_kind;
+
+typedef struct {
+    int32_t n_atoms;
+    const double *Z;            /* [n_atoms] nuclear charges */
+    const double *R;            /* [n_atoms][3] nuclear positions (bohr) */
+    int32_t n_up, n_dn;         /* 0..8 each, n_up + n_dn >= 1 */
+    int32_t basis;              /* qmc_basis_kind */
+    int32_t n_shells;
+    const int32_t *shell_atom;  /* [n_shells] atom of each shell */
+    const int32_t *shell_l;     /* [n_shells] angular momentum 0..2 (s, p, Cartesian d) */
+    const int32_t *shell_kn;    /* [n_shells] Slater radial power r^kn (0 for GTO) */
+    const int32_t *shell_nprim; /* [n_shells] primitives per shell (>= 1) */
+    const double *prim_exp;     /* [sum nprim] zeta (STO) or alpha (GTO), > 0 */
+    const double *prim_coef;    /* [sum nprim] contraction coefficients */
+    int32_t normalize;          /* 1: unit-normalised primitives, 0: raw functions */
+    int32_t n_mo;               /* 1..32 */
+    const double *mo_coef;      /* [n_ao][n_mo] row-major, the effective c * mu */
+    int32_t n_det;              /* >= 1; determinant 0 is the reference */
+    const int32_t *occ_up;      /* [n_det][n_up] MO of each column slot */
+    const int32_t *occ_dn;      /* [n_det][n_dn] */
+    const double *ci;           /* [n_det] CI weights d_n */
+    double jas_a_par;           /* Pade numerator for parallel spins (1/4) */
+    double jas_a_anti;          /* Pade numerator for antiparallel spins (1/2) */
+    double jas_b;               /* Pade denominator parameter (omega), >= 0 */
+} qmc_system_desc;
+
+typedef struct qmc_system qmc_system;
+
+/* Builds a device-resident system on HIP device `device`.  AO order: shells
+   in order; within a shell Cartesian components lexicographic with the
+   x-power first (x, y, z; xx, xy, xz, yy, yz, zz).  Every determinant must
+   differ from the reference by at most two orbitals per spin (single and
+   double excitations, eq. table with k <= 2), and the reference occupations
+   of the two spins must agree on their common slots.  *out is set only on
+   QMC_OK. */
+qmc_status qmc_system_create(const qmc_system_desc *desc, int32_t device, qmc_system **out);
+
+/* Frees the system and its device tables.  NULL is ignored. */
+void qmc_system_destroy(qmc_system *sys);
+
+/* log|Psi|, sign(Psi) and E_L of W walkers.
+   d_X [W][N_e][3]; d_logpsi, d_sign, d_eloc [W].  W = 0 is a no-op.  A walker
+   whose reference determinant is exactly singular gets log|Psi| = -inf,
+   sign = 0 and E_L = NaN. */
+qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d_X, int64_t W,
+                             double *d_logpsi, double *d_sign, double *d_eloc, void *stream);
+
+/* n_steps all-electron Metropolis moves of W walkers, in place.
+   Walker w at step t = step0 + s proposes X' = X + sigma z with z the
+   Box-Muller normals of Philox4x32-10 (key = seed; counter = (walker_offset
+   + w, t low word, t high word, electron)); it accepts when
+   u < exp(2 (log|Psi'| - log|Psi|)), u from counter word 3 = N_e, and then
+   takes (X', log|Psi'|, sign', E_L').  On entry d_logpsi, d_sign and d_eloc
+   must describe d_X (e.g. from qmc_eval_psi_eloc).  d_acc [W][3] gains, per
+   step, (E_L, E_L^2, accepted) of the post-decision state; the caller zeroes
+   it.  Results depend only on (seed, walker_offset + w, t), never on W or on
+   how walkers are batched. */
+qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X, double *d_logpsi,
+                                double *d_sign, double *d_eloc, int64_t W, int32_t n_steps,
+                                double sigma, uint64_t seed, uint64_t step0,
+                                uint32_t walker_offset, double *d_acc, void *stream);
+
+/* Per-walker derivatives for the optimiser and forces (Methods, eqs.
+   nabla_loss and force): d log|Psi| / d theta [W][qmc_param_count] with
+   theta = (primitive exponents, MO coefficients, jas_b), and the nuclear
+   gradient d E_L / d R [W][n_atoms][3].  Either output may be NULL. */
+qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
+                    double *d_deloc_dR, void *stream);
+
+/* Number of variational parameters in the qmc_grad layout. */
+int64_t qmc_param_count(const qmc_system *sys);
+
+/* Device bytes one walker occupies across a Metropolis block (positions,
+   log|Psi|, sign, E_L, accumulators), for admission control. */
+size_t qmc_bytes_per_walker(const qmc_system *sys, int32_t precision);
+
+/* Static text for a status code. */
+const char *qmc_status_string(qmc_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

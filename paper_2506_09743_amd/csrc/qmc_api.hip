@@ -1,0 +1,458 @@
+// C ABI of libqmc: descriptor validation, host-side table construction
+// (normalisation, MO column permutation, excitation canonicalisation,
+// cofactor contribution lists), device residency and kernel launches.
+
+#include "../../include/qmc.h"
+#include "qmc_device.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+namespace qmc {
+hipError_t launch_walkers(bool mc, bool fp32, const DevSystem &S, double *X, double *LP, double *SG,
+                          double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
+                          uint64_t step0, uint32_t woff, double *ACC, hipStream_t st);
+int padded_mo(int n_mo);
+}  // namespace qmc
+
+using qmc::DevSystem;
+
+struct qmc_system {
+    int device;
+    DevSystem S;
+    void *d_mem;        // one allocation holding every table
+    int n_prim;
+    int64_t n_params;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+double factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+double dfactorial(int n) {  // n!!, (-1)!! = 1
+    double f = 1.0;
+    for (int i = n; i > 1; i -= 2) f *= i;
+    return f;
+}
+
+// Unit norm over R^3 of x^a y^b z^c R(r), split into a radial factor (per
+// primitive) and an angular factor (per Cartesian component).  Slater:
+// radial^2 = (2 zeta)^(2n+1) / (2n)! * (2l+1)!! / (4 pi), n = l + kn + 1.
+// Gaussian: radial = (2 alpha / pi)^(3/4) (4 alpha)^(l/2).  Angular:
+// 1 / sqrt((2a-1)!! (2b-1)!! (2c-1)!!).
+double radial_norm(int basis, int l, int kn, double e) {
+    if (basis == QMC_STO) {
+        const int n = l + kn + 1;
+        return sqrt(pow(2.0 * e, 2 * n + 1) / factorial(2 * n) * dfactorial(2 * l + 1) / (4.0 * kPi));
+    }
+    return pow(2.0 * e / kPi, 0.75) * pow(4.0 * e, 0.5 * l);
+}
+
+double angular_norm(int a, int b, int c) {
+    return 1.0 / sqrt(dfactorial(2 * a - 1) * dfactorial(2 * b - 1) * dfactorial(2 * c - 1));
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+// Canonical excitation of one spin of one determinant relative to the
+// reference (after the MO permutation, reference slot k holds MO k).
+struct Excitation {
+    int rank = 0;
+    int h[2] = {0, 0};
+    int p[2] = {0, 0};
+};
+
+// Returns 0 if the determinant is identically zero (repeated MO), -1 if the
+// rank exceeds 2, else 1; *sign is the parity taking the given column order
+// to the canonical one (holes ascending, particles ascending in hole order).
+int canonical_excitation(const std::vector<int> &occ, int n, Excitation *ex, double *sign) {
+    std::vector<int> sorted(occ);
+    std::sort(sorted.begin(), sorted.end());
+    for (int k = 1; k < n; ++k)
+        if (sorted[k] == sorted[k - 1]) return 0;
+    std::vector<char> present(n, 0);
+    std::vector<int> parts;
+    for (int k = 0; k < n; ++k) {
+        if (occ[k] < n)
+            present[occ[k]] = 1;
+        else
+            parts.push_back(occ[k]);
+    }
+    std::vector<int> holes;
+    for (int k = 0; k < n; ++k)
+        if (!present[k]) holes.push_back(k);
+    if ((int)holes.size() > 2) return -1;
+    std::sort(parts.begin(), parts.end());
+    std::vector<int> canon(n);
+    for (int k = 0; k < n; ++k) canon[k] = k;
+    for (size_t a = 0; a < holes.size(); ++a) canon[holes[a]] = parts[a];
+    // parity of the permutation mapping occ -> canon (both hold distinct values)
+    std::map<int, int> pos;
+    for (int k = 0; k < n; ++k) pos[canon[k]] = k;
+    std::vector<int> perm(n);
+    for (int k = 0; k < n; ++k) perm[k] = pos[occ[k]];
+    int swaps = 0;
+    for (int k = 0; k < n; ++k)
+        while (perm[k] != k) {
+            std::swap(perm[k], perm[perm[k]]);
+            ++swaps;
+        }
+    *sign = (swaps & 1) ? -1.0 : 1.0;
+    ex->rank = (int)holes.size();
+    for (size_t a = 0; a < holes.size(); ++a) {
+        ex->h[a] = holes[a];
+        ex->p[a] = parts[a];
+    }
+    return 1;
+}
+
+qmc_status validate(const qmc_system_desc *d) {
+    if (!d) return QMC_EINVAL;
+    if (d->n_atoms < 1 || !d->Z || !d->R) return QMC_EINVAL;
+    if (d->n_up < 0 || d->n_dn < 0 || d->n_up + d->n_dn < 1) return QMC_EINVAL;
+    if (d->basis != QMC_STO && d->basis != QMC_GTO) return QMC_EINVAL;
+    if (d->n_shells < 1 || !d->shell_atom || !d->shell_l || !d->shell_kn || !d->shell_nprim)
+        return QMC_EINVAL;
+    if (!d->prim_exp || !d->prim_coef || !d->mo_coef || !d->ci) return QMC_EINVAL;
+    if (d->n_up > 0 && !d->occ_up) return QMC_EINVAL;
+    if (d->n_dn > 0 && !d->occ_dn) return QMC_EINVAL;
+    if (d->n_mo < 1 || d->n_det < 1) return QMC_EINVAL;
+    if (d->normalize != 0 && d->normalize != 1) return QMC_EINVAL;
+    for (int a = 0; a < d->n_atoms; ++a) {
+        if (!is_finite(d->Z[a]) || !is_finite(d->R[3 * a]) || !is_finite(d->R[3 * a + 1]) || !is_finite(d->R[3 * a + 2]))
+            return QMC_EINVAL;
+    }
+    int n_prim = 0;
+    for (int s = 0; s < d->n_shells; ++s) {
+        if (d->shell_atom[s] < 0 || d->shell_atom[s] >= d->n_atoms) return QMC_EINVAL;
+        if (d->shell_l[s] < 0 || d->shell_kn[s] < 0 || d->shell_nprim[s] < 1) return QMC_EINVAL;
+        if (d->basis == QMC_GTO && d->shell_kn[s] != 0) return QMC_EINVAL;
+        n_prim += d->shell_nprim[s];
+    }
+    for (int p = 0; p < n_prim; ++p)
+        if (!(d->prim_exp[p] > 0.0) || !is_finite(d->prim_exp[p]) || !is_finite(d->prim_coef[p]))
+            return QMC_EINVAL;
+    int n_ao = 0;
+    for (int s = 0; s < d->n_shells; ++s) n_ao += (d->shell_l[s] + 1) * (d->shell_l[s] + 2) / 2;
+    for (int64_t q = 0; q < (int64_t)n_ao * d->n_mo; ++q)
+        if (!is_finite(d->mo_coef[q])) return QMC_EINVAL;
+    for (int n = 0; n < d->n_det; ++n) {
+        if (!is_finite(d->ci[n])) return QMC_EINVAL;
+        for (int k = 0; k < d->n_up; ++k)
+            if (d->occ_up[n * d->n_up + k] < 0 || d->occ_up[n * d->n_up + k] >= d->n_mo) return QMC_EINVAL;
+        for (int k = 0; k < d->n_dn; ++k)
+            if (d->occ_dn[n * d->n_dn + k] < 0 || d->occ_dn[n * d->n_dn + k] >= d->n_mo) return QMC_EINVAL;
+    }
+    if (!is_finite(d->jas_a_par) || !is_finite(d->jas_a_anti) || !is_finite(d->jas_b) || d->jas_b < 0.0)
+        return QMC_EINVAL;
+    return QMC_OK;
+}
+
+template <typename T>
+size_t push_bytes(std::vector<unsigned char> &blob, const T *src, size_t count) {
+    size_t off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + sizeof(T) * count);
+    if (count) memcpy(blob.data() + off, src, sizeof(T) * count);
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qmc_status_string(qmc_status s) {
+    switch (s) {
+        case QMC_OK: return "ok";
+        case QMC_EINVAL: return "invalid argument";
+        case QMC_ENOMEM: return "device allocation failed";
+        case QMC_EDEVICE: return "HIP device error";
+        case QMC_EUNSUPPORTED: return "unsupported by this build";
+    }
+    return "unknown status";
+}
+
+qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_system **out) {
+    if (!out) return QMC_EINVAL;
+    qmc_status st = validate(d);
+    if (st != QMC_OK) return st;
+    const int nu = d->n_up, nd = d->n_dn, ne = nu + nd;
+    if (nu > qmc::kMaxSpin || nd > qmc::kMaxSpin) return QMC_EUNSUPPORTED;
+    for (int s = 0; s < d->n_shells; ++s)
+        if (d->shell_l[s] > 2) return QMC_EUNSUPPORTED;
+    const int nmo_pad = qmc::padded_mo(d->n_mo);
+    if (nmo_pad < 0 || d->n_mo < std::max(nu, nd)) return QMC_EUNSUPPORTED;
+
+    // --- MO permutation putting the reference orbitals first ----------------
+    const int *ref_long = nu >= nd ? d->occ_up : d->occ_dn;
+    const int *ref_short = nu >= nd ? d->occ_dn : d->occ_up;
+    const int n_long = std::max(nu, nd), n_short = std::min(nu, nd);
+    for (int k = 0; k < n_short; ++k)
+        if (ref_long[k] != ref_short[k]) return QMC_EUNSUPPORTED;
+    std::vector<int> new_of_old(d->n_mo, -1), old_of_new;
+    for (int k = 0; k < n_long; ++k) {
+        if (new_of_old[ref_long[k]] >= 0) return QMC_EUNSUPPORTED;  // reference det vanishes
+        new_of_old[ref_long[k]] = k;
+        old_of_new.push_back(ref_long[k]);
+    }
+    for (int m = 0; m < d->n_mo; ++m)
+        if (new_of_old[m] < 0) {
+            new_of_old[m] = (int)old_of_new.size();
+            old_of_new.push_back(m);
+        }
+
+    // --- canonical excitations, folded signs ----------------------------------
+    std::vector<int> dets;
+    std::vector<double> ci;
+    std::vector<Excitation> ex_up, ex_dn;
+    for (int n = 0; n < d->n_det; ++n) {
+        Excitation eu, ed;
+        double su = 1.0, sd = 1.0;
+        std::vector<int> ou(nu), od(nd);
+        for (int k = 0; k < nu; ++k) ou[k] = new_of_old[d->occ_up[n * nu + k]];
+        for (int k = 0; k < nd; ++k) od[k] = new_of_old[d->occ_dn[n * nd + k]];
+        int ru = canonical_excitation(ou, nu, &eu, &su);
+        int rd = canonical_excitation(od, nd, &ed, &sd);
+        if (ru < 0 || rd < 0) return QMC_EUNSUPPORTED;
+        if (ru == 0 || rd == 0) continue;  // identically zero determinant
+        if (n == 0 && (eu.rank != 0 || ed.rank != 0)) return QMC_EUNSUPPORTED;
+        ex_up.push_back(eu);
+        ex_dn.push_back(ed);
+        ci.push_back(d->ci[n] * su * sd);
+        const Excitation *e2[2] = {&eu, &ed};
+        for (int s = 0; s < 2; ++s) {
+            dets.push_back(e2[s]->rank);
+            dets.push_back(e2[s]->h[0]);
+            dets.push_back(e2[s]->h[1]);
+            dets.push_back(e2[s]->p[0]);
+            dets.push_back(e2[s]->p[1]);
+        }
+    }
+    const int n_det = (int)ci.size();
+
+    // --- cofactor contribution lists: C_s[k][v] = dS / dT_s[k][v] -------------
+    // key (spin, k, v) -> contributions (det, sign, h', p'); sign 0 = unit cofactor
+    std::map<std::tuple<int, int, int>, std::vector<int4>> ent;
+    for (int n = 0; n < n_det; ++n) {
+        const Excitation *e2[2] = {&ex_up[n], &ex_dn[n]};
+        for (int s = 0; s < 2; ++s) {
+            const Excitation &e = *e2[s];
+            if (e.rank == 1) {
+                ent[std::make_tuple(s, e.h[0], e.p[0])].push_back(make_int4(n, 0, 0, 0));
+            } else if (e.rank == 2) {
+                ent[std::make_tuple(s, e.h[0], e.p[0])].push_back(make_int4(n, 1, e.h[1], e.p[1]));
+                ent[std::make_tuple(s, e.h[1], e.p[1])].push_back(make_int4(n, 1, e.h[0], e.p[0]));
+                ent[std::make_tuple(s, e.h[0], e.p[1])].push_back(make_int4(n, -1, e.h[1], e.p[0]));
+                ent[std::make_tuple(s, e.h[1], e.p[0])].push_back(make_int4(n, -1, e.h[0], e.p[1]));
+            }
+        }
+    }
+    std::vector<int4> entries, contribs;
+    for (auto &kv : ent) {
+        entries.push_back(make_int4(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                                    (int)contribs.size()));
+        for (const int4 &c : kv.second) contribs.push_back(c);
+    }
+    entries.push_back(make_int4(0, 0, 0, (int)contribs.size()));
+    const int n_entries = (int)entries.size() - 1;
+
+    // --- basis tables -------------------------------------------------------
+    std::vector<int4> shells;
+    std::vector<double2> prims;
+    std::vector<double> angf;  // per AO angular factor
+    int p0 = 0;
+    for (int s = 0; s < d->n_shells; ++s) {
+        const int l = d->shell_l[s], kn = d->shell_kn[s], np = d->shell_nprim[s];
+        shells.push_back(make_int4(d->shell_atom[s], l, kn, np));
+        for (int q = 0; q < np; ++q) {
+            const double e = d->prim_exp[p0 + q];
+            const double c = d->prim_coef[p0 + q] * (d->normalize ? radial_norm(d->basis, l, kn, e) : 1.0);
+            prims.push_back(make_double2(e, c));
+        }
+        p0 += np;
+        for (int a = l; a >= 0; --a)
+            for (int b = l - a; b >= 0; --b) angf.push_back(d->normalize ? angular_norm(a, b, l - a - b) : 1.0);
+    }
+    const int n_ao = (int)angf.size();
+    std::vector<double> mo((size_t)n_ao * nmo_pad, 0.0);
+    std::vector<float> mo_f((size_t)n_ao * nmo_pad, 0.0f);
+    for (int mu = 0; mu < n_ao; ++mu)
+        for (int m = 0; m < d->n_mo; ++m) {
+            const double v = d->mo_coef[(size_t)mu * d->n_mo + old_of_new[m]] * angf[mu];
+            mo[(size_t)mu * nmo_pad + m] = v;
+            mo_f[(size_t)mu * nmo_pad + m] = (float)v;
+        }
+    std::vector<double> atoms;
+    double vnn = 0.0;
+    for (int a = 0; a < d->n_atoms; ++a) {
+        atoms.push_back(d->R[3 * a]);
+        atoms.push_back(d->R[3 * a + 1]);
+        atoms.push_back(d->R[3 * a + 2]);
+        atoms.push_back(d->Z[a]);
+        for (int b = 0; b < a; ++b) {
+            const double dx = d->R[3 * a] - d->R[3 * b], dy = d->R[3 * a + 1] - d->R[3 * b + 1],
+                         dz = d->R[3 * a + 2] - d->R[3 * b + 2];
+            vnn += d->Z[a] * d->Z[b] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    }
+
+    std::vector<unsigned char> blob;
+    const size_t o_atoms = push_bytes(blob, atoms.data(), atoms.size());
+    const size_t o_shells = push_bytes(blob, shells.data(), shells.size());
+    const size_t o_prims = push_bytes(blob, prims.data(), prims.size());
+    const size_t o_mo = push_bytes(blob, mo.data(), mo.size());
+    const size_t o_mof = push_bytes(blob, mo_f.data(), mo_f.size());
+    const size_t o_dets = push_bytes(blob, dets.data(), dets.size());
+    const size_t o_ci = push_bytes(blob, ci.data(), ci.size());
+    const size_t o_ent = push_bytes(blob, entries.data(), entries.size());
+    const size_t o_con = push_bytes(blob, contribs.data(), contribs.size());
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return QMC_EDEVICE;
+    if (device < 0 || device >= ndev) return QMC_EINVAL;
+    DeviceGuard g(device);
+    if (!g.ok) return QMC_EDEVICE;
+    void *dm = nullptr;
+    if (hipMalloc(&dm, blob.size()) != hipSuccess) return QMC_ENOMEM;
+    if (hipMemcpy(dm, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dm);
+        return QMC_EDEVICE;
+    }
+    qmc_system *sys = new (std::nothrow) qmc_system();
+    if (!sys) {
+        (void)hipFree(dm);
+        return QMC_ENOMEM;
+    }
+    unsigned char *base = (unsigned char *)dm;
+    DevSystem &S = sys->S;
+    S.n_up = nu;
+    S.n_dn = nd;
+    S.ne = ne;
+    S.n_atoms = d->n_atoms;
+    S.n_shells = d->n_shells;
+    S.n_ao = n_ao;
+    S.n_mo = d->n_mo;
+    S.n_det = n_det;
+    S.n_entries = n_entries;
+    int G = 1;
+    while (G < std::max(nu, nd)) G <<= 1;
+    S.G = G;
+    S.LW = 2 * G;
+    S.WPW = qmc::kWave / S.LW;
+    S.nmo_pad = nmo_pad;
+    S.basis = d->basis;
+    S.a_par = d->jas_a_par;
+    S.a_anti = d->jas_a_anti;
+    S.b = d->jas_b;
+    S.vnn = vnn;
+    S.atoms = (const double *)(base + o_atoms);
+    S.shells = (const int4 *)(base + o_shells);
+    S.prims = (const double2 *)(base + o_prims);
+    S.mo = (const double *)(base + o_mo);
+    S.mo_f = (const float *)(base + o_mof);
+    S.dets = (const int *)(base + o_dets);
+    S.ci = (const double *)(base + o_ci);
+    S.entries = (const int4 *)(base + o_ent);
+    S.contribs = (const int4 *)(base + o_con);
+    sys->device = device;
+    sys->d_mem = dm;
+    sys->n_prim = (int)prims.size();
+    sys->n_params = (int64_t)prims.size() + (int64_t)n_ao * d->n_mo + 1;
+    *out = sys;
+    return QMC_OK;
+}
+
+void qmc_system_destroy(qmc_system *sys) {
+    if (!sys) return;
+    {
+        DeviceGuard g(sys->device);
+        (void)hipFree(sys->d_mem);
+    }
+    delete sys;
+}
+
+static qmc_status check_walk_args(qmc_system *sys, int32_t precision, int64_t W) {
+    if (!sys) return QMC_EINVAL;
+    if (W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
+    if (precision != QMC_FP64 && precision != QMC_MIXED_FP32 && precision != QMC_MIXED_BF16)
+        return QMC_EINVAL;
+    if (precision == QMC_MIXED_BF16) return QMC_EUNSUPPORTED;
+    return QMC_OK;
+}
+
+qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d_X, int64_t W,
+                             double *d_logpsi, double *d_sign, double *d_eloc, void *stream) {
+    qmc_status st = check_walk_args(sys, precision, W);
+    if (st != QMC_OK) return st;
+    if (W == 0) return QMC_OK;
+    if (!d_X || !d_logpsi || !d_sign || !d_eloc) return QMC_EINVAL;
+    DeviceGuard g(sys->device);
+    if (!g.ok) return QMC_EDEVICE;
+    hipError_t e = qmc::launch_walkers(false, precision == QMC_MIXED_FP32, sys->S, (double *)d_X,
+                                       d_logpsi, d_sign, d_eloc, W, 0, 0.0, 0, 0, 0, nullptr,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
+}
+
+qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X, double *d_logpsi,
+                                double *d_sign, double *d_eloc, int64_t W, int32_t n_steps,
+                                double sigma, uint64_t seed, uint64_t step0, uint32_t walker_offset,
+                                double *d_acc, void *stream) {
+    qmc_status st = check_walk_args(sys, precision, W);
+    if (st != QMC_OK) return st;
+    if (n_steps < 0 || !is_finite(sigma) || sigma < 0.0) return QMC_EINVAL;
+    if ((uint64_t)walker_offset + (uint64_t)W > 0x100000000ull) return QMC_EINVAL;
+    if (W == 0 || n_steps == 0) return QMC_OK;
+    if (!d_X || !d_logpsi || !d_sign || !d_eloc || !d_acc) return QMC_EINVAL;
+    DeviceGuard g(sys->device);
+    if (!g.ok) return QMC_EDEVICE;
+    hipError_t e = qmc::launch_walkers(true, precision == QMC_MIXED_FP32, sys->S, d_X, d_logpsi,
+                                       d_sign, d_eloc, W, n_steps, sigma, seed, step0, walker_offset,
+                                       d_acc, (hipStream_t)stream);
+    return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
+}
+
+qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
+                    double *d_deloc_dR, void *stream) {
+    (void)d_X;
+    (void)d_dlogpsi;
+    (void)d_deloc_dR;
+    (void)stream;
+    if (!sys || W < 0) return QMC_EINVAL;
+    return QMC_EUNSUPPORTED;
+}
+
+int64_t qmc_param_count(const qmc_system *sys) { return sys ? sys->n_params : -1; }
+
+size_t qmc_bytes_per_walker(const qmc_system *sys, int32_t precision) {
+    (void)precision;
+    if (!sys) return 0;
+    // positions + (log|Psi|, sign, E_L) + three accumulators, all FP64
+    return (size_t)sys->S.ne * 3 * sizeof(double) + 6 * sizeof(double);
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// Device-side system tables and launch helpers shared by the HIP kernels and
+// the C ABI host code of libqmc (never by the oracle).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qmc {
+
+// Largest spin block handled by one lane group (lanes per spin = next power
+// of two >= max(n_up, n_dn) <= 8).
+constexpr int kMaxSpin = 8;
+constexpr int kWave = 64;
+// Ints per determinant record: (rank, h1, h2, p1, p2) for spin up, then down.
+constexpr int kDetInts = 10;
+
+// Everything a kernel needs about one system; passed by value as a kernel
+// argument.  Pointers refer to one device allocation owned by the handle.
+struct DevSystem {
+    int n_up, n_dn, ne, n_atoms, n_shells, n_ao, n_mo, n_det, n_entries;
+    int G;    // lanes per spin group (power of two >= max(n_up, n_dn))
+    int LW;   // lanes per walker = 2 G
+    int WPW;  // walkers per wave = 64 / LW
+    int nmo_pad;  // row stride of the MO coefficient tables
+    int basis;    // 0 Slater, 1 Gaussian
+    double a_par, a_anti, b, vnn;
+    const double *atoms;    // [n_atoms][4]: x, y, z, Z
+    const int4 *shells;     // [n_shells]: atom, l, kn, nprim
+    const double2 *prims;   // [n_prim]: exponent, coefficient x radial normalisation
+    const double *mo;       // [n_ao][nmo_pad]: permuted columns, angular factors folded in
+    const float *mo_f;      // same, FP32
+    const int *dets;        // [n_det][kDetInts]
+    const double *ci;       // [n_det], canonicalisation signs folded in
+    const int4 *entries;    // [n_entries + 1]: spin, slot k, MO v, first contribution
+    const int4 *contribs;   // [n_contrib]: det, cofactor sign (0 = unit), h', p'
+};
+
+// Doubles of LDS one walker uses: T tables and cofactor tables for both spin
+// groups, the walker's electron positions and one pivot row per group.
+__host__ __device__ inline int walker_lds_doubles(const DevSystem &S, int nmo) {
+    return 4 * S.G * nmo + 3 * S.LW + 2 * nmo;
+}
+
+}  // namespace qmc

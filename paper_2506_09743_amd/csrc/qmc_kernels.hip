@@ -1,0 +1,599 @@
+// HIP kernels (gfx950) for Slater-Jastrow VMC: local energy evaluation and
+// all-electron Metropolis blocks.
+//
+// Work decomposition.  One wave of 64 lanes holds 64 / (2G) walkers; each
+// walker owns 2G consecutive lanes, G per spin, and lane i of a spin group
+// owns electron i of that spin.  A lane evaluates its electron's atomic
+// orbitals and molecular orbitals in registers, the Slater matrices are
+// factorised across the lanes of a group (row = electron), and the walker's
+// scalars are reduced across its lanes with cross-lane shuffles.  Walkers
+// never interact, so a walker's results do not depend on its neighbours.
+//
+// Kinetic energy (appendix on local energies).  With Psi = exp(J) Sigma the
+// Laplacian splits into lap J + |grad J|^2 + 2 grad J . grad Sigma / Sigma +
+// lap Sigma / Sigma.  Because every determinant is linear in the row of one
+// electron, grad_e Sigma / Sigma = sum_m a_e[m] grad phi_m(r_e) and
+// lap_e Sigma / Sigma = sum_m a_e[m] lap phi_m(r_e) with a_e[m] =
+// d log Sigma / d phi_m(r_e) (this is the per-electron Jacobi trace of
+// eq. claudia_trace summed over the CI expansion).  a_e follows from the
+// low-rank excited-determinant algebra of eq. table: with T = A0^-1 Phi,
+// every excited determinant is D0 det T[H,P] (k <= 2), Sigma = D0 S with
+// S = sum_n d_n det T_up[H,P] det T_dn[H,P], and the CI-weighted cofactors
+// C = dS/dT give a_e[v] = (A0^-T C)[e,v] / S on virtual orbitals and
+// a_e[k] = A0^-1[k,e] - (A0^-T C T^T)[e,k] / S on reference orbitals.
+// Only A0 is ever inverted, as in the paper's accelerated scheme.
+
+#include "qmc_device.h"
+
+#include <math.h>
+
+namespace qmc {
+namespace {
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m); }
+
+// Sum over the LW lanes of a walker (LW a power of two, walkers aligned).
+__device__ __forceinline__ double walker_sum(double v, int LW) {
+    for (int off = 1; off < LW; off <<= 1) v += shfl_xor_d(v, off);
+    return v;
+}
+
+__device__ __forceinline__ int walker_sum_i(int v, int LW) {
+    for (int off = 1; off < LW; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+struct Lane {
+    int lane;    // 0..63
+    int wloc;    // walker slot in the wave
+    int lw;      // lane within walker, 0..LW-1
+    int grp;     // 0 spin up, 1 spin down
+    int i;       // index within the spin group
+    int e;       // electron index within the walker
+    int nsig;    // electrons of this spin
+    int gbase;   // first lane of the group
+    bool wvalid; // walker index < W
+    bool active; // owns a real electron of a valid walker
+};
+
+__device__ __forceinline__ Lane make_lane(const DevSystem &S, int64_t wave_first_walker, int64_t W,
+                                          int64_t *walker) {
+    Lane L;
+    L.lane = threadIdx.x;
+    L.wloc = L.lane / S.LW;
+    L.lw = L.lane % S.LW;
+    L.grp = L.lw / S.G;
+    L.i = L.lw % S.G;
+    L.nsig = L.grp == 0 ? S.n_up : S.n_dn;
+    L.e = L.grp == 0 ? L.i : S.n_up + L.i;
+    L.gbase = L.lane - L.i;
+    const int64_t w = wave_first_walker + L.wloc;
+    *walker = w;
+    L.wvalid = (L.wloc < S.WPW) && (w < W);
+    L.active = L.wvalid && (L.i < L.nsig);
+    return L;
+}
+
+// Determinant ratio det T[H,P] of one spin, rank k <= 2, from the walker's
+// T table (row = slot, column = MO, stride NMO).
+template <int NMO>
+__device__ __forceinline__ double ratio(const double *T, const int *d) {
+    const int k = d[0];
+    if (k == 0) return 1.0;
+    const double a = T[d[1] * NMO + d[3]];
+    if (k == 1) return a;
+    return a * T[d[2] * NMO + d[4]] - T[d[1] * NMO + d[4]] * T[d[2] * NMO + d[3]];
+}
+
+// Accumulates one AO's five channels into the lane's MO registers.
+template <int NMO, typename RT>
+__device__ __forceinline__ void mo_accum(RT (&mo)[5][NMO], const RT *crow, RT v, RT gx, RT gy,
+                                         RT gz, RT lp) {
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) {
+        const RT c = crow[m];
+        mo[0][m] += v * c;
+        mo[1][m] += gx * c;
+        mo[2][m] += gy * c;
+        mo[3][m] += gz * c;
+        mo[4][m] += lp * c;
+    }
+}
+
+template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
+template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
+
+template <typename RT> __device__ __forceinline__ const RT *mo_table(const DevSystem &S);
+template <> __device__ __forceinline__ const double *mo_table<double>(const DevSystem &S) { return S.mo; }
+template <> __device__ __forceinline__ const float *mo_table<float>(const DevSystem &S) { return S.mo_f; }
+
+// AO value / gradient / Laplacian of the lane's electron and their MO
+// contraction.  For AO = P(x,y,z) R(r) with a degree-l monomial P:
+//   grad = R grad P + P (R'/r) d,   lap = R lap P + P (R'' + (2l+2) R'/r).
+// Slater R = r^kn exp(-zeta r): R'/R = kn/r - zeta.  Gaussian R =
+// exp(-alpha r^2): R'/r = -2 alpha R, R'' + (2l+2) R'/r = (4 alpha^2 r^2 -
+// (4l+6) alpha) R.  Normalisations are folded into the primitive
+// coefficients (radial) and the MO rows (angular) at system creation.
+template <int NMO, typename RT>
+__device__ __forceinline__ void ao_mo(const DevSystem &S, double x0, double x1, double x2,
+                                      RT (&mo)[5][NMO]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) mo[c][m] = RT(0);
+    const RT *C = mo_table<RT>(S);
+    int p = 0, mu = 0;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        // Displacement in FP64, cast afterwards (reduced forms only round it).
+        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
+        const RT r2 = dx * dx + dy * dy + dz * dz;
+        const RT r = sqrt(r2);
+        const RT rinv = RT(1) / r;
+        const int l = si.y, kn = si.z;
+        RT Rv = 0, Rd = 0, Rl = 0;
+        if (S.basis == 0) {
+            const RT fl = RT(2 * l + 2);
+            for (int q = 0; q < si.w; ++q) {
+                const double2 pe = S.prims[p + q];
+                const RT ex = RT(pe.x);
+                RT f = RT(pe.y) * rt_exp<RT>(-ex * r);
+                for (int t = 0; t < kn; ++t) f *= r;
+                const RT g = RT(kn) * rinv - ex;
+                Rv += f;
+                Rd += f * g * rinv;
+                Rl += f * (g * g - RT(kn) * rinv * rinv + fl * g * rinv);
+            }
+        } else {
+            const RT fl = RT(4 * l + 6);
+            for (int q = 0; q < si.w; ++q) {
+                const double2 pe = S.prims[p + q];
+                const RT ex = RT(pe.x);
+                const RT f = RT(pe.y) * rt_exp<RT>(-ex * r2);
+                Rv += f;
+                Rd -= RT(2) * ex * f;
+                Rl += f * (RT(4) * ex * ex * r2 - fl * ex);
+            }
+        }
+        p += si.w;
+        const RT *crow = C + (size_t)mu * S.nmo_pad;
+        const RT gx = Rd * dx, gy = Rd * dy, gz = Rd * dz;
+        if (l == 0) {
+            mo_accum<NMO, RT>(mo, crow, Rv, gx, gy, gz, Rl);
+            mu += 1;
+        } else if (l == 1) {
+            mo_accum<NMO, RT>(mo, crow, dx * Rv, Rv + dx * gx, dx * gy, dx * gz, dx * Rl);
+            mo_accum<NMO, RT>(mo, crow + S.nmo_pad, dy * Rv, dy * gx, Rv + dy * gy, dy * gz, dy * Rl);
+            mo_accum<NMO, RT>(mo, crow + 2 * S.nmo_pad, dz * Rv, dz * gx, dz * gy, Rv + dz * gz, dz * Rl);
+            mu += 3;
+        } else {
+            const int st = S.nmo_pad;
+            RT P;
+            P = dx * dx;  // xx
+            mo_accum<NMO, RT>(mo, crow, P * Rv, RT(2) * dx * Rv + P * gx, P * gy, P * gz,
+                              RT(2) * Rv + P * Rl);
+            P = dx * dy;  // xy
+            mo_accum<NMO, RT>(mo, crow + st, P * Rv, dy * Rv + P * gx, dx * Rv + P * gy, P * gz, P * Rl);
+            P = dx * dz;  // xz
+            mo_accum<NMO, RT>(mo, crow + 2 * st, P * Rv, dz * Rv + P * gx, P * gy, dx * Rv + P * gz, P * Rl);
+            P = dy * dy;  // yy
+            mo_accum<NMO, RT>(mo, crow + 3 * st, P * Rv, P * gx, RT(2) * dy * Rv + P * gy, P * gz,
+                              RT(2) * Rv + P * Rl);
+            P = dy * dz;  // yz
+            mo_accum<NMO, RT>(mo, crow + 4 * st, P * Rv, P * gx, dz * Rv + P * gy, dy * Rv + P * gz, P * Rl);
+            P = dz * dz;  // zz
+            mo_accum<NMO, RT>(mo, crow + 5 * st, P * Rv, P * gx, P * gy, RT(2) * dz * Rv + P * gz,
+                              RT(2) * Rv + P * Rl);
+            mu += 6;
+        }
+    }
+}
+
+struct WalkerResult {
+    double logpsi, sign, eloc;
+};
+
+// Evaluates log|Psi|, sign and E_L of the lane's walker at the electron
+// positions held by its lanes (x0, x1, x2 of the lane's electron).  Every
+// lane of the block must call it (it contains block barriers); results are
+// identical on all lanes of a walker.
+template <int NMO, typename RT>
+__device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
+                                    double x1, double x2) {
+    double *sT = wsm;                        // [2][G][NMO]
+    double *sC = sT + 2 * S.G * NMO;         // [2][G][NMO]
+    double *sPos = sC + 2 * S.G * NMO;       // [LW][3]
+    double *sPiv = sPos + 3 * S.LW;          // [2][NMO]
+    double *Tg = sT + L.grp * S.G * NMO;
+    double *Cg = sC + L.grp * S.G * NMO;
+    double *piv_row = sPiv + L.grp * NMO;
+
+    if (!L.active) {  // a far point keeps idle lanes finite
+        x0 = 100.0;
+        x1 = 100.0;
+        x2 = 100.0;
+    }
+    sPos[3 * L.lw + 0] = x0;
+    sPos[3 * L.lw + 1] = x1;
+    sPos[3 * L.lw + 2] = x2;
+    __syncthreads();
+
+    // ---- Pade e-e Jastrow and Coulomb terms of this electron -------------
+    double J = 0.0, gJ0 = 0.0, gJ1 = 0.0, gJ2 = 0.0, lapJ = 0.0, vpot = 0.0;
+    if (L.active) {
+        for (int j = 0; j < S.ne; ++j) {
+            if (j == L.e) continue;
+            const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
+            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double rinv = 1.0 / r;
+            const bool same = (j < S.n_up) == (L.e < S.n_up);
+            const double a = same ? S.a_par : S.a_anti;
+            const double den = 1.0 + S.b * r, dinv = 1.0 / den;
+            const double k1 = a * dinv * dinv;              // K'(r)
+            const double k2 = -2.0 * a * S.b * dinv * dinv * dinv;  // K''(r)
+            J += 0.5 * a * r * dinv;
+            gJ0 += k1 * d0 * rinv;
+            gJ1 += k1 * d1 * rinv;
+            gJ2 += k1 * d2 * rinv;
+            lapJ += k2 + 2.0 * k1 * rinv;
+            vpot += 0.5 * rinv;
+        }
+        for (int a = 0; a < S.n_atoms; ++a) {
+            const double *A = S.atoms + 4 * a;
+            const double d0 = x0 - A[0], d1 = x1 - A[1], d2 = x2 - A[2];
+            vpot -= A[3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+    }
+
+    // ---- AOs and MOs: mo[c][m], c = value, d/dx, d/dy, d/dz, Laplacian ----
+    RT mo[5][NMO];
+    ao_mo<NMO, RT>(S, x0, x1, x2, mo);
+
+    // ---- In-place Gauss-Jordan of the reference matrix across the group --
+    // Row = this electron's MO values.  Pivot column j (reference orbital j
+    // after the create-time column permutation) is replaced by the column of
+    // the inverse, so at the end the row of slot s holds A0^-1[s][.] in
+    // columns < n (indexed by the slot of each electron) and T[s][v] =
+    // (A0^-1 Phi)[s][v] in the virtual columns v >= n.
+    double a[NMO];
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) a[m] = double(mo[0][m]);
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    bool done = !L.active;
+    int slot = -1;
+    double dprod = 1.0;
+    bool singular = false;
+    constexpr int JMAX = kMaxSpin < NMO ? kMaxSpin : NMO;
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        if (j >= nmax) break;
+        const bool work = j < L.nsig;
+        double cand = (work && !done) ? fabs(a[j]) : -1.0;
+        int cl = L.i;
+        for (int off = 1; off < S.G; off <<= 1) {
+            const double oc = shfl_xor_d(cand, off);
+            const int ol = __shfl_xor(cl, off);
+            if (oc > cand || (oc == cand && ol < cl)) {
+                cand = oc;
+                cl = ol;
+            }
+        }
+        const double piv = __shfl(a[j], L.gbase + cl);
+        const bool ok = work && cand > 0.0;
+        if (work && !ok) singular = true;
+        const bool is_piv = ok && L.active && L.i == cl;
+        if (is_piv) {
+            // publish the unscaled pivot row, then scale this row in place
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) piv_row[m] = a[m];
+            const double inv = 1.0 / piv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) a[m] *= inv;
+            a[j] = inv;
+            done = true;
+            slot = j;
+        }
+        if (work) dprod *= piv;
+        __syncthreads();
+        if (ok && L.active && !is_piv) {
+            // multiplier as in Doolittle elimination: equal rows cancel exactly
+            const double f = a[j] / piv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) a[m] -= f * piv_row[m];
+            a[j] = -f;
+        }
+        __syncthreads();
+    }
+    if (L.active && slot >= 0) {
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) Tg[slot * NMO + m] = a[m];
+    }
+    // Permutation parity (slot s <- electron row): inversions within the group.
+    int inv_cnt = 0;
+    for (int ip = 0; ip < S.G; ++ip) {
+        const int so = __shfl(slot, L.gbase + ip);
+        if (L.active && ip > L.i && so >= 0 && so < slot) ++inv_cnt;
+    }
+    for (int off = 1; off < S.G; off <<= 1) inv_cnt += __shfl_xor(inv_cnt, off);
+    const double det_sign = ((inv_cnt & 1) ? -1.0 : 1.0) * (dprod < 0.0 ? -1.0 : 1.0);
+    const double det_log = log(fabs(dprod));
+    // zero the cofactor tables before they are accumulated
+    for (int q = L.lw; q < 2 * S.G * NMO; q += S.LW) sC[q] = 0.0;
+    __syncthreads();
+
+    const int gup = L.lane - L.lw, gdn = gup + S.G;
+    const double logD_up = __shfl(det_log, gup), logD_dn = __shfl(det_log, gdn);
+    const double sgn_up = __shfl(det_sign, gup), sgn_dn = __shfl(det_sign, gdn);
+    const int sing_walker = walker_sum_i(singular ? 1 : 0, S.LW);
+
+    // ---- S = sum_n d_n rho_up(n) rho_dn(n) ---------------------------------
+    const double *Tup = sT, *Tdn = sT + S.G * NMO;
+    double Sp = 0.0;
+    if (L.wvalid) {
+        for (int n = L.lw; n < S.n_det; n += S.LW) {
+            const int *d = S.dets + n * kDetInts;
+            Sp += S.ci[n] * ratio<NMO>(Tup, d) * ratio<NMO>(Tdn, d + 5);
+        }
+    }
+    const double Ssum = walker_sum(Sp, S.LW);
+
+    // ---- cofactor tables C_sigma[k][v] = dS / dT_sigma[k][v] ---------------
+    if (L.wvalid) {
+        for (int t = L.lw; t < S.n_entries; t += S.LW) {
+            const int4 en = S.entries[t];
+            const int end = S.entries[t + 1].w;
+            const double *Ts = en.x == 0 ? Tup : Tdn;
+            const double *To = en.x == 0 ? Tdn : Tup;
+            const int oth = en.x == 0 ? 5 : 0;
+            double val = 0.0;
+            for (int c = en.w; c < end; ++c) {
+                const int4 cb = S.contribs[c];
+                const int *d = S.dets + cb.x * kDetInts;
+                const double cof = cb.y == 0 ? 1.0 : double(cb.y) * Ts[cb.z * NMO + cb.w];
+                val += S.ci[cb.x] * ratio<NMO>(To, d + oth) * cof;
+            }
+            sC[en.x * S.G * NMO + en.y * NMO + en.z] = val;
+        }
+    }
+    __syncthreads();
+
+    // ---- a_e = d log Sigma / d phi(r_e), then grad and Laplacian of Sigma --
+    double gS0 = 0.0, gS1 = 0.0, gS2 = 0.0, lapS = 0.0;
+    if (L.active) {
+        const int sl = slot < 0 ? 0 : slot;
+        double ainv[JMAX];
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) ainv[k] = (k < L.nsig) ? Tg[k * NMO + sl] : 0.0;
+        const double Sinv = 1.0 / Ssum;
+        // virtual orbitals: a_e[v] = (A0^-T C)[e][v] / S
+        double av[NMO];
+#pragma unroll
+        for (int v = 0; v < NMO; ++v) {
+            double acc = 0.0;
+            if (v >= L.nsig) {
+#pragma unroll
+                for (int k = 0; k < JMAX; ++k)
+                    if (k < L.nsig) acc += ainv[k] * Cg[k * NMO + v];
+            }
+            av[v] = acc * Sinv;
+        }
+        // reference orbitals: a_e[k] = A0^-1[k][e] - sum_v T[k][v] a_e[v]
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) {
+            if (k < L.nsig) {
+                double h = 0.0;
+#pragma unroll
+                for (int v = 0; v < NMO; ++v)
+                    if (v >= L.nsig) h += Tg[k * NMO + v] * av[v];
+                av[k] = ainv[k] - h;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) {
+            gS0 += av[m] * double(mo[1][m]);
+            gS1 += av[m] * double(mo[2][m]);
+            gS2 += av[m] * double(mo[3][m]);
+            lapS += av[m] * double(mo[4][m]);
+        }
+    }
+
+    // ---- local energy and log|Psi| ------------------------------------------
+    double part = 0.0;
+    if (L.active) {
+        const double kin = lapS + lapJ + gJ0 * gJ0 + gJ1 * gJ1 + gJ2 * gJ2 +
+                           2.0 * (gJ0 * gS0 + gJ1 * gS1 + gJ2 * gS2);
+        part = -0.5 * kin + vpot;
+    }
+    const double eloc = walker_sum(part, S.LW) + S.vnn;
+    const double Jw = walker_sum(J, S.LW);
+    WalkerResult res;
+    if (sing_walker > 0 || Ssum == 0.0 || !L.wvalid) {
+        res.logpsi = -INFINITY;
+        res.sign = 0.0;
+        res.eloc = NAN;
+    } else {
+        res.logpsi = Jw + logD_up + logD_dn + log(fabs(Ssum));
+        res.sign = sgn_up * sgn_dn * (Ssum < 0.0 ? -1.0 : 1.0);
+        res.eloc = eloc;
+    }
+    __syncthreads();  // LDS is reused by the next evaluation
+    return res;
+}
+
+template <int NMO, typename RT>
+__global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
+                                                 double *__restrict__ LP, double *__restrict__ SG,
+                                                 double *__restrict__ EL) {
+    extern __shared__ double smem[];
+    int64_t w;
+    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+    double *wsm = smem + L.wloc * walker_lds_doubles(S, NMO);
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    if (L.active) {
+        const double *p = X + (w * S.ne + L.e) * 3;
+        x0 = p[0];
+        x1 = p[1];
+        x2 = p[2];
+    }
+    const WalkerResult r = eval_walker<NMO, RT>(S, L, wsm, x0, x1, x2);
+    if (L.wvalid && L.lw == 0) {
+        LP[w] = r.logpsi;
+        SG[w] = r.sign;
+        EL[w] = r.eloc;
+    }
+}
+
+template <int NMO, typename RT>
+__global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__restrict__ X,
+                                                      double *__restrict__ LP, double *__restrict__ SG,
+                                                      double *__restrict__ EL, int64_t W, int n_steps,
+                                                      double sigma, uint64_t seed, uint64_t step0,
+                                                      uint32_t walker_offset, double *__restrict__ ACC) {
+    extern __shared__ double smem[];
+    int64_t w;
+    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+    double *wsm = smem + L.wloc * walker_lds_doubles(S, NMO);
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    if (L.active) {
+        const double *p = X + (w * S.ne + L.e) * 3;
+        x0 = p[0];
+        x1 = p[1];
+        x2 = p[2];
+    }
+    double lp = 0.0, sg = 0.0, el = 0.0;
+    if (L.wvalid) {
+        lp = LP[w];
+        sg = SG[w];
+        el = EL[w];
+    }
+    // running accumulators start from the caller's values, so a block split
+    // at any step gives the same sums as one block
+    double s_e = 0.0, s_e2 = 0.0, s_acc = 0.0;
+    if (L.wvalid) {
+        s_e = ACC[3 * w + 0];
+        s_e2 = ACC[3 * w + 1];
+        s_acc = ACC[3 * w + 2];
+    }
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t wid = walker_offset + (uint32_t)w;
+    const double s32 = 1.0 / 4294967296.0;
+    const double two_pi = 6.283185307179586;
+    for (int t = 0; t < n_steps; ++t) {
+        const uint64_t step = step0 + (uint64_t)t;
+        uint32_t c[4] = {wid, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)L.e};
+        philox4x32_10(c, k0, k1);
+        const double u0 = ((double)c[0] + 0.5) * s32, u1 = ((double)c[1] + 0.5) * s32;
+        const double u2 = ((double)c[2] + 0.5) * s32, u3 = ((double)c[3] + 0.5) * s32;
+        const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+        const double z0 = r0 * cos(two_pi * u1), z1 = r0 * sin(two_pi * u1);
+        const double z2 = r1 * cos(two_pi * u3);
+        // no FMA contraction: X + sigma z rounds the product, then the sum
+        const double y0 = __dadd_rn(x0, __dmul_rn(sigma, z0));
+        const double y1 = __dadd_rn(x1, __dmul_rn(sigma, z1));
+        const double y2 = __dadd_rn(x2, __dmul_rn(sigma, z2));
+        uint32_t ca[4] = {wid, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)S.ne};
+        philox4x32_10(ca, k0, k1);
+        const uint64_t bits = ((((uint64_t)ca[0]) << 32) | (uint64_t)ca[1]) >> 11;
+        const double u = (double)bits * (1.0 / 9007199254740992.0);
+
+        const WalkerResult r = eval_walker<NMO, RT>(S, L, wsm, y0, y1, y2);
+        const bool acc = isfinite(r.logpsi) && (u < exp(2.0 * (r.logpsi - lp)));
+        if (acc) {
+            x0 = y0;
+            x1 = y1;
+            x2 = y2;
+            lp = r.logpsi;
+            sg = r.sign;
+            el = r.eloc;
+        }
+        s_e = __dadd_rn(s_e, el);
+        s_e2 = __dadd_rn(s_e2, __dmul_rn(el, el));
+        s_acc += acc ? 1.0 : 0.0;
+    }
+    if (L.active) {
+        double *p = X + (w * S.ne + L.e) * 3;
+        p[0] = x0;
+        p[1] = x1;
+        p[2] = x2;
+    }
+    if (L.wvalid && L.lw == 0) {
+        LP[w] = lp;
+        SG[w] = sg;
+        EL[w] = el;
+        ACC[3 * w + 0] = s_e;
+        ACC[3 * w + 1] = s_e2;
+        ACC[3 * w + 2] = s_acc;
+    }
+}
+
+}  // namespace
+
+// ---- launch dispatch ---------------------------------------------------------
+
+static int nmo_bucket(int n_mo) {
+    const int b[] = {4, 8, 12, 16, 20, 24, 32};
+    for (int v : b)
+        if (n_mo <= v) return v;
+    return -1;
+}
+
+int padded_mo(int n_mo) { return nmo_bucket(n_mo); }
+
+template <int NMO, typename RT>
+static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL,
+                           int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
+                           uint32_t woff, double *ACC, hipStream_t st) {
+    const int64_t blocks = (W + S.WPW - 1) / S.WPW;
+    const size_t lds = (size_t)S.WPW * walker_lds_doubles(S, NMO) * sizeof(double);
+    if (mc)
+        hipLaunchKernelGGL((k_metropolis<NMO, RT>), dim3((unsigned)blocks), dim3(kWave), lds, st, S, X,
+                           LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
+    else
+        hipLaunchKernelGGL((k_eval<NMO, RT>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
+                           (const double *)X, W, LP, SG, EL);
+    return hipGetLastError();
+}
+
+template <typename RT>
+static hipError_t launch_rt(bool mc, const DevSystem &S, double *X, double *LP, double *SG,
+                            double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
+                            uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
+    switch (S.nmo_pad) {
+#define QMC_CASE(N) \
+    case N: return launch_t<N, RT>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
+#undef QMC_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_walkers(bool mc, bool fp32, const DevSystem &S, double *X, double *LP, double *SG,
+                          double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
+                          uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
+    if (fp32)
+        return launch_rt<float>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+    return launch_rt<double>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+}
+
+}  // namespace qmc

@@ -1,0 +1,94 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/qmc.h declares, and rejects invalid descriptors before touching a
+device."""
+import os
+import re
+
+import pytest
+
+from paper_2506_09743_amd import qmc, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qmc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ("qmc_system_create", "qmc_eval_psi_eloc", "qmc_metropolis_block", "qmc_grad"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = qmc.lib()
+    names = _declared()
+    assert set(names) == set(qmc.EXPORTS)
+    for n in names:
+        assert getattr(L, n) is not None
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4):
+        assert qmc.status_string(code)
+    assert qmc.status_string(-99) == "unknown status"
+
+
+def _bad(mutate):
+    d = synth.make_system("LiH")
+    mutate(d)
+    return d
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda d: d.__setitem__("jas_b", -0.5),
+    lambda d: d.__setitem__("prim_exp", -d["prim_exp"]),
+    lambda d: d.__setitem__("shell_atom", d["shell_atom"] + 5),
+    lambda d: d.__setitem__("occ_up", d["occ_up"] + 100),
+    lambda d: d.__setitem__("ci", d["ci"] * float("nan")),
+    lambda d: d.__setitem__("normalize", 3),
+], ids=["negative b", "negative exponent", "atom index", "MO index", "NaN CI", "normalize flag"])
+def test_create_rejects_invalid_descriptor(mutate):
+    with pytest.raises(qmc.QmcError) as ei:
+        qmc.System(_bad(mutate))
+    assert ei.value.status == qmc.QMC_EINVAL
+
+
+def test_create_rejects_unsupported_shapes():
+    f = synth.single_atom(1.0, 1.0, l=3)  # f shells are beyond the compiled kernels
+    with pytest.raises(qmc.QmcError) as ei:
+        qmc.System(f)
+    assert ei.value.status == qmc.QMC_EUNSUPPORTED
+    big = synth.make_system("CO")
+    big["n_up"] = 9
+    with pytest.raises(qmc.QmcError) as ei:
+        qmc.System(big)
+    assert ei.value.status in (qmc.QMC_EUNSUPPORTED, qmc.QMC_EINVAL)
+
+
+def test_null_arguments_rejected():
+    import ctypes as C
+    L = qmc.lib()
+    assert L.qmc_system_create(None, 0, C.byref(C.c_void_p())) == qmc.QMC_EINVAL
+    assert L.qmc_eval_psi_eloc(None, 0, None, 1, None, None, None, None) == qmc.QMC_EINVAL
+    assert L.qmc_metropolis_block(None, 0, None, None, None, None, 1, 1, 0.2, 0, 0, 0, None, None) == qmc.QMC_EINVAL
+    assert L.qmc_grad(None, None, 1, None, None, None) == qmc.QMC_EINVAL
+    assert L.qmc_param_count(None) == -1
+    assert L.qmc_bytes_per_walker(None, 0) == 0
+    L.qmc_system_destroy(None)
+
+
+def test_valid_create_needs_a_device():
+    import torch
+    d = synth.make_system("CO")
+    if torch.cuda.is_available():
+        s = qmc.System(d)
+        assert s.param_count == d["prim_exp"].size + d["mo_coef"].size + 1
+        s.close()
+    else:
+        with pytest.raises(qmc.QmcError) as ei:
+            qmc.System(d)
+        assert ei.value.status == qmc.QMC_EDEVICE
