@@ -1,0 +1,270 @@
+"""Throughput of all-electron Metropolis sampling with Psi and E_L on one
+MI355X: walker-steps/s for the synthetic CO system at 65536 walkers.
+
+One benchmark step is one all-electron Metropolis step of every walker:
+Philox proposal, Psi and E_L at the proposal, accept/reject, accumulation of
+E_L.  Steps are launched as blocks of --chunk steps (qmc_metropolis_block);
+walker state stays in HBM between blocks.  The timed region starts from an
+equilibrated state (burn-in) with all inputs resident on the device.
+
+Prints one JSON line (see the keys below).  The FP64 form is `value`; the
+mixed FP32 form (FP32 AOs and MO contraction, FP64 determinants and E_L) is
+reported beside it with its energy errors.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
+PEAK_HBM = 8.0e12          # bytes/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "co_metropolis_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_09743_amd", "csrc", f)
+                  for f in ("qmc_kernels.hip", "qmc_device.h")]
+
+
+def flops_per_walker_step(sysd) -> dict:
+    """Algorithmic FP operations of one walker-step (FMA = 2, add/mul/div = 1,
+    exp/log/sqrt/sin/cos = 1), counted from the method's formulas at the cost
+    of the low-rank excited-determinant scheme; pairs counted once."""
+    from paper_2506_09743_amd import synth
+    ne, nu, nd = synth.n_elec(sysd), int(sysd["n_up"]), int(sysd["n_dn"])
+    na = len(sysd["Z"])
+    nmo = int(np.asarray(sysd["mo_coef"]).shape[1])
+    nao = synth.n_ao(sysd)
+    ndet = len(sysd["ci"])
+    sto = sysd["basis"] == "sto"
+    f = {}
+    f["proposal"] = ne * (6 + 3 * 2 + 7)                    # x + sigma z, Box-Muller
+    per_prim = 17 if sto else 13
+    n_prim = int(np.sum(sysd["shell_nprim"]))
+    n_sh = len(sysd["shell_l"])
+    f["ao"] = ne * (n_sh * 10 + n_prim * per_prim + nao * 10)
+    f["mo"] = ne * 2 * 5 * nao * nmo                         # 5 channels
+    f["lu"] = sum(2 * n * n * nmo for n in (nu, nd))         # Gauss-Jordan on [A0 | Phi]
+    f["dets"] = ndet * 8                                      # k<=2 minors, CI sum
+    n_ex = 0
+    for occ, n in ((sysd["occ_up"], nu), (sysd["occ_dn"], nd)):
+        for row in np.asarray(occ):
+            k = int(np.sum(np.asarray(row) >= n))
+            n_ex += {0: 0, 1: 1, 2: 4}.get(k, 4)
+    f["cofactors"] = n_ex * 6
+    f["traces"] = sum(n * (4 * n * (nmo - n) + 8 * nmo) for n in (nu, nd))
+    f["pairs"] = (ne * (ne - 1) // 2) * 25 + ne * na * 9
+    f["eloc"] = ne * 15 + 10
+    f["accept"] = 6
+    f["total"] = sum(f.values())
+    return f
+
+
+def hbm_bytes_per_launch(sysd, W: int) -> int:
+    """Walker state read and written once per launch: X, log|Psi|, sign, E_L
+    and three accumulators, FP64."""
+    from paper_2506_09743_amd import synth
+    per = (3 * synth.n_elec(sysd) + 6) * 8
+    return 2 * per * W
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha") != kernel_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(sysd, X_host, lp, sg, el, seed, target_s: float) -> dict:
+    """The FP64 oracle's Metropolis block on the host cores, on a bounded
+    sample of the same equilibrated walkers."""
+    import oracle
+    o = oracle.OracleSystem(sysd)
+    threads = oracle.max_threads()
+    nw = min(4096, X_host.shape[0])
+    probe_w, probe_s = min(256, nw), 2
+    t0 = time.perf_counter()
+    o.metropolis(X_host[:probe_w], lp[:probe_w], sg[:probe_w], el[:probe_w], probe_s, 0.2, seed)
+    rate = probe_w * probe_s / max(time.perf_counter() - t0, 1e-9)
+    steps = max(1, min(200, int(target_s * rate / nw)))
+    t0 = time.perf_counter()
+    o.metropolis(X_host[:nw], lp[:nw], sg[:nw], el[:nw], steps, 0.2, seed, step0=10_000_000)
+    dt = time.perf_counter() - t0
+    return {"value": nw * steps / dt, "unit": "walker-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nw} of the equilibrated CO walkers x {steps} Metropolis steps "
+                      f"({dt:.1f} s, explicit per-determinant LU)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=10, help="Metropolis steps per launch")
+    ap.add_argument("--walkers", type=int, default=65536)
+    ap.add_argument("--burnin", type=int, default=200)
+    ap.add_argument("--system", default="CO")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pmc-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the walkers of a multi-GPU run would be independent "
+              "shards with one 32-byte all-reduce per block, which this build does not launch.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_2506_09743_amd import qmc, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    sysd = synth.make_system(args.system)
+    W = args.walkers
+    seed = synth.PHILOX_SEED[args.system]
+    system = qmc.System(sysd, device=0)
+    X = torch.from_numpy(synth.init_walkers(sysd, W, synth.WALKER_SEED[args.system])).to(dev)
+
+    def run_steps(state, n, step0, precision, acc, events=None):
+        s = 0
+        while s < n:
+            c = min(args.chunk, n - s)
+            if events is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+            system.metropolis(*state, c, 0.2, seed, step0=step0 + s, acc=acc, precision=precision)
+            if events is not None:
+                e1.record()
+                events.append((e0, e1, c))
+            s += c
+        return step0 + n
+
+    # equilibrate in FP64
+    lp, sg, el = system.eval(X)
+    state = [X, lp, sg, el]
+    acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+    step = run_steps(state, args.burnin, 0, "fp64", acc)
+    torch.cuda.synchronize()
+    X_eq = X.clone()
+    lp_eq, sg_eq, el_eq = lp.clone(), sg.clone(), el.clone()
+
+    results = {}
+    for form in (["fp64"] if args.no_mixed else ["fp64", "fp32"]):
+        st = [X_eq.clone(), lp_eq.clone(), sg_eq.clone(), el_eq.clone()]
+        if form != "fp64":  # the mixed chain carries its own log|Psi| and E_L
+            st[1], st[2], st[3] = system.eval(st[0], precision=form)
+        acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+        s0 = run_steps(st, args.warmup, step, form, acc)
+        acc.zero_()
+        events = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(st, args.steps, s0, form, acc, events)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        launch_ms = np.array([a.elapsed_time(b) for a, b, _ in events])
+        per_step_ms = np.array([a.elapsed_time(b) / c for a, b, c in events])
+        a = acc.cpu().numpy()
+        results[form] = dict(
+            value=W * args.steps / dt, ms_per_step=1e3 * dt / args.steps,
+            launch_ms_mean=float(launch_ms.mean()), launch_steps=args.chunk,
+            p50_ms=float(np.percentile(launch_ms, 50)), p99_ms=float(np.percentile(launch_ms, 99)),
+            kernel_ms_per_step=float(per_step_ms.mean()),
+            mean_energy=float(np.nanmean(a[:, 0]) / args.steps),
+            acceptance=float(a[:, 2].mean() / args.steps))
+
+    # errors against the oracle on identical (FP64-chain) configurations
+    Xn = X_eq.cpu().numpy()
+    idx = np.random.default_rng(0).choice(W, size=min(2048, W), replace=False)
+    o = oracle.OracleSystem(sysd)
+    rlp, rsg, rel = o.eval(Xn[idx])
+    errors = {}
+    for form in results:
+        glp, gsg, gel = [t.cpu().numpy() for t in system.eval(X_eq, precision=form)]
+        d = gel[idx] - rel
+        ok = np.isfinite(d)
+        errors[form] = dict(max_abs_dE_L=float(np.max(np.abs(d[ok]))),
+                            median_abs_dE_L=float(np.median(np.abs(d[ok]))),
+                            mean_energy_err_vs_oracle=float(abs(np.mean(gel[idx][ok]) - np.mean(rel[ok]))),
+                            max_rel_dlogpsi=float(np.max(np.abs(glp[idx] - rlp) / np.maximum(1, np.abs(rlp)))))
+        if form != "fp64":
+            g64 = system.eval(X_eq, precision="fp64")[2].cpu().numpy()
+            m = np.isfinite(gel) & np.isfinite(g64)
+            errors[form]["mean_energy_err_vs_fp64_all_walkers"] = float(abs(gel[m].mean() - g64[m].mean()))
+        results[form].update(errors[form])
+
+    fl = flops_per_walker_step(sysd)
+    main_form = results["fp64"]
+    launch_s = main_form["launch_ms_mean"] * 1e-3
+    flops_launch = fl["total"] * W * args.chunk
+    achieved = flops_launch / launch_s
+    traffic = measured_traffic()
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
+                "kernel": "k_metropolis<20,double> (qmc_metropolis_block)",
+                "flops_per_walker_step": fl["total"], "walker_steps_per_launch": W * args.chunk,
+                "hbm_bytes_per_launch_algorithmic": hbm_bytes_per_launch(sysd, W),
+                "launch_ms_mean": main_form["launch_ms_mean"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(sysd, Xn, lp_eq.cpu().numpy(), sg_eq.cpu().numpy(), el_eq.cpu().numpy(),
+                           seed, args.cpu_seconds)
+
+    if args.pmc_calibration_mib:
+        n = args.pmc_calibration_mib * (1 << 20) // 8
+        a_ = torch.ones(n, dtype=torch.float64, device=dev)
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "walker-steps/s (Psi+E_L) CO 64k walkers, mixed vs FP64 at stated err; p50/p99",
+        "value": main_form["value"], "unit": "walker-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_form["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.system} all-electron VMC, {W} walkers, Metropolis sigma 0.2, "
+                               f"{args.chunk} steps per launch, after {args.burnin} burn-in steps",
+                   "walkers": W, "electrons": synth.n_elec(sysd), "aos": synth.n_ao(sysd),
+                   "mos": int(np.asarray(sysd['mo_coef']).shape[1]), "dets": len(sysd["ci"])},
+        "p50_ms": main_form["p50_ms"], "p99_ms": main_form["p99_ms"],
+        "latency_unit": f"ms per launch of {args.chunk} steps x {W} walkers",
+        "forms": results,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    system.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -35,10 +35,4 @@ struct DevSystem {
     const int4 *contribs;   // [n_contrib]: det, cofactor sign (0 = unit), h', p'
 };
 
-// Doubles of LDS one walker uses: T tables and cofactor tables for both spin
-// groups, the walker's electron positions and one pivot row per group.
-__host__ __device__ inline int walker_lds_doubles(const DevSystem &S, int nmo) {
-    return 4 * S.G * nmo + 3 * S.LW + 2 * nmo;
-}
-
 }  // namespace qmc

@@ -103,21 +103,6 @@ __device__ __forceinline__ double ratio(const double *T, const int *d) {
     return a * T[d[2] * NMO + d[4]] - T[d[1] * NMO + d[4]] * T[d[2] * NMO + d[3]];
 }
 
-// Accumulates one AO's five channels into the lane's MO registers.
-template <int NMO, typename RT>
-__device__ __forceinline__ void mo_accum(RT (&mo)[5][NMO], const RT *crow, RT v, RT gx, RT gy,
-                                         RT gz, RT lp) {
-#pragma unroll
-    for (int m = 0; m < NMO; ++m) {
-        const RT c = crow[m];
-        mo[0][m] += v * c;
-        mo[1][m] += gx * c;
-        mo[2][m] += gy * c;
-        mo[3][m] += gz * c;
-        mo[4][m] += lp * c;
-    }
-}
-
 template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
 template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp(x); }
 template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
@@ -126,92 +111,165 @@ template <typename RT> __device__ __forceinline__ const RT *mo_table(const DevSy
 template <> __device__ __forceinline__ const double *mo_table<double>(const DevSystem &S) { return S.mo; }
 template <> __device__ __forceinline__ const float *mo_table<float>(const DevSystem &S) { return S.mo_f; }
 
-// AO value / gradient / Laplacian of the lane's electron and their MO
-// contraction.  For AO = P(x,y,z) R(r) with a degree-l monomial P:
-//   grad = R grad P + P (R'/r) d,   lap = R lap P + P (R'' + (2l+2) R'/r).
-// Slater R = r^kn exp(-zeta r): R'/R = kn/r - zeta.  Gaussian R =
-// exp(-alpha r^2): R'/r = -2 alpha R, R'' + (2l+2) R'/r = (4 alpha^2 r^2 -
-// (4l+6) alpha) R.  Normalisations are folded into the primitive
-// coefficients (radial) and the MO rows (angular) at system creation.
-template <int NMO, typename RT>
-__device__ __forceinline__ void ao_mo(const DevSystem &S, double x0, double x1, double x2,
-                                      RT (&mo)[5][NMO]) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c)
-#pragma unroll
-        for (int m = 0; m < NMO; ++m) mo[c][m] = RT(0);
-    const RT *C = mo_table<RT>(S);
-    int p = 0, mu = 0;
-    for (int sh = 0; sh < S.n_shells; ++sh) {
-        const int4 si = S.shells[sh];
-        const double *A = S.atoms + 4 * si.x;
-        // Displacement in FP64, cast afterwards (reduced forms only round it).
-        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
-        const RT r2 = dx * dx + dy * dy + dz * dz;
-        const RT r = sqrt(r2);
-        const RT rinv = RT(1) / r;
-        const int l = si.y, kn = si.z;
-        RT Rv = 0, Rd = 0, Rl = 0;
-        if (S.basis == 0) {
-            const RT fl = RT(2 * l + 2);
-            for (int q = 0; q < si.w; ++q) {
-                const double2 pe = S.prims[p + q];
-                const RT ex = RT(pe.x);
-                RT f = RT(pe.y) * rt_exp<RT>(-ex * r);
-                for (int t = 0; t < kn; ++t) f *= r;
+// Radial part of one shell at distance r: R, and with DERIV also R'/r and
+// R'' + (2l+2) R'/r.  Slater R = sum_p c_p r^kn exp(-zeta_p r), so R'/R =
+// kn/r - zeta; Gaussian R = sum_p c_p exp(-alpha_p r^2), so R'/r = -2 alpha R
+// and R'' + (2l+2) R'/r = (4 alpha^2 r^2 - (4l+6) alpha) R.  The primitive
+// coefficients carry the radial normalisation.
+template <typename RT, bool DERIV>
+__device__ __forceinline__ void shell_radial(const DevSystem &S, int p, int np, int l, int kn, RT r,
+                                             RT r2, RT rinv, RT &Rv, RT &Rd, RT &Rl) {
+    Rv = RT(0);
+    Rd = RT(0);
+    Rl = RT(0);
+    if (S.basis == 0) {
+        const RT fl = RT(2 * l + 2);
+        RT rk = RT(1);
+        for (int t = 0; t < kn; ++t) rk *= r;
+        for (int q = 0; q < np; ++q) {
+            const double2 pe = S.prims[p + q];
+            const RT ex = RT(pe.x);
+            const RT f = RT(pe.y) * rk * rt_exp<RT>(-ex * r);
+            Rv += f;
+            if (DERIV) {
                 const RT g = RT(kn) * rinv - ex;
-                Rv += f;
                 Rd += f * g * rinv;
                 Rl += f * (g * g - RT(kn) * rinv * rinv + fl * g * rinv);
             }
-        } else {
-            const RT fl = RT(4 * l + 6);
-            for (int q = 0; q < si.w; ++q) {
-                const double2 pe = S.prims[p + q];
-                const RT ex = RT(pe.x);
-                const RT f = RT(pe.y) * rt_exp<RT>(-ex * r2);
-                Rv += f;
+        }
+    } else {
+        const RT fl = RT(4 * l + 6);
+        for (int q = 0; q < np; ++q) {
+            const double2 pe = S.prims[p + q];
+            const RT ex = RT(pe.x);
+            const RT f = RT(pe.y) * rt_exp<RT>(-ex * r2);
+            Rv += f;
+            if (DERIV) {
                 Rd -= RT(2) * ex * f;
                 Rl += f * (RT(4) * ex * ex * r2 - fl * ex);
             }
         }
+    }
+}
+
+// Pass 1: MO values phi_m(r_e) = sum_mu C[mu][m] chi_mu(r_e) of the lane's
+// electron (Methods, AO and MO layers).  AO = P(x,y,z) R(r) with P a
+// Cartesian monomial; angular normalisations are folded into the rows of C.
+template <int NMO, typename RT>
+__device__ __forceinline__ void mo_values(const DevSystem &S, double x0, double x1, double x2,
+                                          RT (&phi)[NMO]) {
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) phi[m] = RT(0);
+    const RT *C = mo_table<RT>(S);
+    int p = 0;
+    const RT *crow = C;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        // displacement in FP64, cast afterwards
+        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
+        const RT r2 = dx * dx + dy * dy + dz * dz;
+        const RT r = sqrt(r2);
+        RT Rv, Rd, Rl;
+        shell_radial<RT, false>(S, p, si.w, si.y, si.z, r, r2, RT(0), Rv, Rd, Rl);
         p += si.w;
-        const RT *crow = C + (size_t)mu * S.nmo_pad;
-        const RT gx = Rd * dx, gy = Rd * dy, gz = Rd * dz;
-        if (l == 0) {
-            mo_accum<NMO, RT>(mo, crow, Rv, gx, gy, gz, Rl);
-            mu += 1;
-        } else if (l == 1) {
-            mo_accum<NMO, RT>(mo, crow, dx * Rv, Rv + dx * gx, dx * gy, dx * gz, dx * Rl);
-            mo_accum<NMO, RT>(mo, crow + S.nmo_pad, dy * Rv, dy * gx, Rv + dy * gy, dy * gz, dy * Rl);
-            mo_accum<NMO, RT>(mo, crow + 2 * S.nmo_pad, dz * Rv, dz * gx, dz * gy, Rv + dz * gz, dz * Rl);
-            mu += 3;
-        } else {
-            const int st = S.nmo_pad;
+        const int nc = (si.y + 1) * (si.y + 2) / 2;
+        for (int c = 0; c < nc; ++c) {
             RT P;
-            P = dx * dx;  // xx
-            mo_accum<NMO, RT>(mo, crow, P * Rv, RT(2) * dx * Rv + P * gx, P * gy, P * gz,
-                              RT(2) * Rv + P * Rl);
-            P = dx * dy;  // xy
-            mo_accum<NMO, RT>(mo, crow + st, P * Rv, dy * Rv + P * gx, dx * Rv + P * gy, P * gz, P * Rl);
-            P = dx * dz;  // xz
-            mo_accum<NMO, RT>(mo, crow + 2 * st, P * Rv, dz * Rv + P * gx, P * gy, dx * Rv + P * gz, P * Rl);
-            P = dy * dy;  // yy
-            mo_accum<NMO, RT>(mo, crow + 3 * st, P * Rv, P * gx, RT(2) * dy * Rv + P * gy, P * gz,
-                              RT(2) * Rv + P * Rl);
-            P = dy * dz;  // yz
-            mo_accum<NMO, RT>(mo, crow + 4 * st, P * Rv, P * gx, dz * Rv + P * gy, dy * Rv + P * gz, P * Rl);
-            P = dz * dz;  // zz
-            mo_accum<NMO, RT>(mo, crow + 5 * st, P * Rv, P * gx, P * gy, RT(2) * dz * Rv + P * gz,
-                              RT(2) * Rv + P * Rl);
-            mu += 6;
+            if (si.y == 0) P = RT(1);
+            else if (si.y == 1) P = c == 0 ? dx : (c == 1 ? dy : dz);
+            else {
+                const RT u = (c < 3) ? dx : (c < 5 ? dy : dz);
+                const RT v = (c == 0) ? dx : (c == 1 || c == 3) ? dy : dz;
+                P = u * v;
+            }
+            const RT val = P * Rv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) phi[m] += val * crow[m];
+            crow += S.nmo_pad;
         }
     }
+}
+
+// Pass 2: grad_e Sigma / Sigma and lap_e Sigma / Sigma.  With a_e[m] =
+// d log Sigma / d phi_m(r_e) and t_mu = sum_m C[mu][m] a_e[m], both are
+// sum_mu t_mu (grad, lap) chi_mu(r_e); for chi = P R:
+//   grad chi = R grad P + P (R'/r) d,   lap chi = R lap P + P (R'' + (2l+2) R'/r).
+template <int NMO, typename RT>
+__device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, double x1, double x2,
+                                             const double (&av)[NMO], double &g0, double &g1,
+                                             double &g2, double &lap) {
+    const RT *C = mo_table<RT>(S);
+    RT a[NMO];
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) a[m] = RT(av[m]);
+    int p = 0;
+    const RT *crow = C;
+    double G0 = 0.0, G1 = 0.0, G2 = 0.0, L = 0.0;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
+        const RT r2 = dx * dx + dy * dy + dz * dz;
+        const RT r = sqrt(r2);
+        const RT rinv = RT(1) / r;
+        RT Rv, Rd, Rl;
+        shell_radial<RT, true>(S, p, si.w, si.y, si.z, r, r2, rinv, Rv, Rd, Rl);
+        p += si.w;
+        const int nc = (si.y + 1) * (si.y + 2) / 2;
+        for (int c = 0; c < nc; ++c) {
+            RT t = RT(0);
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) t += crow[m] * a[m];
+            crow += S.nmo_pad;
+            // monomial, its gradient and Laplacian
+            RT P, Px, Py, Pz, PL;
+            if (si.y == 0) {
+                P = RT(1); Px = Py = Pz = PL = RT(0);
+            } else if (si.y == 1) {
+                P = c == 0 ? dx : (c == 1 ? dy : dz);
+                Px = c == 0 ? RT(1) : RT(0);
+                Py = c == 1 ? RT(1) : RT(0);
+                Pz = c == 2 ? RT(1) : RT(0);
+                PL = RT(0);
+            } else {
+                // xx, xy, xz, yy, yz, zz
+                const int iu = (c < 3) ? 0 : (c < 5 ? 1 : 2);
+                const int iv = (c == 0) ? 0 : (c == 1 || c == 3) ? 1 : 2;
+                const RT u = iu == 0 ? dx : (iu == 1 ? dy : dz);
+                const RT v = iv == 0 ? dx : (iv == 1 ? dy : dz);
+                P = u * v;
+                Px = (iu == 0 ? v : RT(0)) + (iv == 0 ? u : RT(0));
+                Py = (iu == 1 ? v : RT(0)) + (iv == 1 ? u : RT(0));
+                Pz = (iu == 2 ? v : RT(0)) + (iv == 2 ? u : RT(0));
+                PL = iu == iv ? RT(2) : RT(0);
+            }
+            const RT PRd = P * Rd;
+            G0 += double(t * (Rv * Px + PRd * dx));
+            G1 += double(t * (Rv * Py + PRd * dy));
+            G2 += double(t * (Rv * Pz + PRd * dz));
+            L += double(t * (Rv * PL + P * Rl));
+        }
+    }
+    g0 = G0;
+    g1 = G1;
+    g2 = G2;
+    lap = L;
 }
 
 struct WalkerResult {
     double logpsi, sign, eloc;
 };
+
+// LDS of one walker: T tables [2][G][NMO], then a region shared by the
+// positions + pivot rows (before the determinant stage) and the cofactor
+// tables [2][G][NMO] (after it).
+template <int NMO>
+__host__ __device__ inline int walker_lds(const DevSystem &S) {
+    const int t = 2 * S.G * NMO;
+    const int a = 3 * S.LW + 2 * NMO;
+    return t + (a > t ? a : t);
+}
 
 // Evaluates log|Psi|, sign and E_L of the lane's walker at the electron
 // positions held by its lanes (x0, x1, x2 of the lane's electron).  Every
@@ -221,12 +279,14 @@ template <int NMO, typename RT>
 __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
                                     double x1, double x2) {
     double *sT = wsm;                        // [2][G][NMO]
-    double *sC = sT + 2 * S.G * NMO;         // [2][G][NMO]
-    double *sPos = sC + 2 * S.G * NMO;       // [LW][3]
-    double *sPiv = sPos + 3 * S.LW;          // [2][NMO]
+    double *sX = sT + 2 * S.G * NMO;         // shared region
+    double *sC = sX;                         // [2][G][NMO] after the elimination
+    double *sPos = sX;                       // [LW][3] before it
+    double *sPiv = sX + 3 * S.LW;            // [2][NMO] during it
     double *Tg = sT + L.grp * S.G * NMO;
     double *Cg = sC + L.grp * S.G * NMO;
     double *piv_row = sPiv + L.grp * NMO;
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
 
     if (!L.active) {  // a far point keeps idle lanes finite
         x0 = 100.0;
@@ -249,8 +309,8 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
             const double rinv = 1.0 / r;
             const bool same = (j < S.n_up) == (L.e < S.n_up);
             const double a = same ? S.a_par : S.a_anti;
-            const double den = 1.0 + S.b * r, dinv = 1.0 / den;
-            const double k1 = a * dinv * dinv;              // K'(r)
+            const double dinv = 1.0 / (1.0 + S.b * r);
+            const double k1 = a * dinv * dinv;                      // K'(r)
             const double k2 = -2.0 * a * S.b * dinv * dinv * dinv;  // K''(r)
             J += 0.5 * a * r * dinv;
             gJ0 += k1 * d0 * rinv;
@@ -266,25 +326,25 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
         }
     }
 
-    // ---- AOs and MOs: mo[c][m], c = value, d/dx, d/dy, d/dz, Laplacian ----
-    RT mo[5][NMO];
-    ao_mo<NMO, RT>(S, x0, x1, x2, mo);
-
-    // ---- In-place Gauss-Jordan of the reference matrix across the group --
-    // Row = this electron's MO values.  Pivot column j (reference orbital j
-    // after the create-time column permutation) is replaced by the column of
-    // the inverse, so at the end the row of slot s holds A0^-1[s][.] in
-    // columns < n (indexed by the slot of each electron) and T[s][v] =
-    // (A0^-1 Phi)[s][v] in the virtual columns v >= n.
+    // ---- pass 1: MO values of this electron ------------------------------
     double a[NMO];
+    {
+        RT phi[NMO];
+        mo_values<NMO, RT>(S, x0, x1, x2, phi);
 #pragma unroll
-    for (int m = 0; m < NMO; ++m) a[m] = double(mo[0][m]);
-    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+        for (int m = 0; m < NMO; ++m) a[m] = double(phi[m]);
+    }
+
+    // ---- in-place Gauss-Jordan of the reference matrix across the group --
+    // Row = this electron's MO values.  Pivot column j (reference orbital j
+    // after the create-time column permutation) is overwritten by the
+    // inverse, so at the end the row of slot s holds A0^-1[s][slot(e)] in
+    // the columns < n and T[s][v] = (A0^-1 Phi)[s][v] in the virtual columns.
+    constexpr int JMAX = kMaxSpin < NMO ? kMaxSpin : NMO;
     bool done = !L.active;
     int slot = -1;
     double dprod = 1.0;
     bool singular = false;
-    constexpr int JMAX = kMaxSpin < NMO ? kMaxSpin : NMO;
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
         if (j >= nmax) break;
@@ -338,16 +398,16 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
     for (int off = 1; off < S.G; off <<= 1) inv_cnt += __shfl_xor(inv_cnt, off);
     const double det_sign = ((inv_cnt & 1) ? -1.0 : 1.0) * (dprod < 0.0 ? -1.0 : 1.0);
     const double det_log = log(fabs(dprod));
-    // zero the cofactor tables before they are accumulated
+    // the shared region now becomes the cofactor tables: zero them
     for (int q = L.lw; q < 2 * S.G * NMO; q += S.LW) sC[q] = 0.0;
     __syncthreads();
 
-    const int gup = L.lane - L.lw, gdn = gup + S.G;
-    const double logD_up = __shfl(det_log, gup), logD_dn = __shfl(det_log, gdn);
-    const double sgn_up = __shfl(det_sign, gup), sgn_dn = __shfl(det_sign, gdn);
+    const int wb = L.lane - L.lw;
+    const double logD_up = __shfl(det_log, wb), logD_dn = __shfl(det_log, wb + S.G);
+    const double sgn_up = __shfl(det_sign, wb), sgn_dn = __shfl(det_sign, wb + S.G);
     const int sing_walker = walker_sum_i(singular ? 1 : 0, S.LW);
 
-    // ---- S = sum_n d_n rho_up(n) rho_dn(n) ---------------------------------
+    // ---- S = sum_n d_n det T_up[H,P] det T_dn[H,P] ----------------------
     const double *Tup = sT, *Tdn = sT + S.G * NMO;
     double Sp = 0.0;
     if (L.wvalid) {
@@ -378,45 +438,49 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
     }
     __syncthreads();
 
-    // ---- a_e = d log Sigma / d phi(r_e), then grad and Laplacian of Sigma --
-    double gS0 = 0.0, gS1 = 0.0, gS2 = 0.0, lapS = 0.0;
-    if (L.active) {
+    // ---- a_e = d log Sigma / d phi(r_e) ------------------------------------
+    // virtual orbitals: a_e[v] = (A0^-T C)[e][v] / S (C vanishes on the
+    // reference columns); reference orbitals: a_e[k] = A0^-1[k][e] -
+    // sum_v T[k][v] a_e[v].
+    double av[NMO];
+    {
         const int sl = slot < 0 ? 0 : slot;
         double ainv[JMAX];
 #pragma unroll
-        for (int k = 0; k < JMAX; ++k) ainv[k] = (k < L.nsig) ? Tg[k * NMO + sl] : 0.0;
-        const double Sinv = 1.0 / Ssum;
-        // virtual orbitals: a_e[v] = (A0^-T C)[e][v] / S
-        double av[NMO];
-#pragma unroll
-        for (int v = 0; v < NMO; ++v) {
-            double acc = 0.0;
-            if (v >= L.nsig) {
-#pragma unroll
-                for (int k = 0; k < JMAX; ++k)
-                    if (k < L.nsig) acc += ainv[k] * Cg[k * NMO + v];
+        for (int k = 0; k < JMAX; ++k) {
+            ainv[k] = 0.0;
+            if (k < nmax) {
+                const double t = Tg[k * NMO + sl];
+                ainv[k] = (k < L.nsig && L.active) ? t : 0.0;
             }
-            av[v] = acc * Sinv;
         }
-        // reference orbitals: a_e[k] = A0^-1[k][e] - sum_v T[k][v] a_e[v]
+        const double Sinv = 1.0 / Ssum;
+#pragma unroll
+        for (int v = 0; v < NMO; ++v) av[v] = 0.0;
 #pragma unroll
         for (int k = 0; k < JMAX; ++k) {
-            if (k < L.nsig) {
-                double h = 0.0;
+            if (k >= nmax) break;
 #pragma unroll
-                for (int v = 0; v < NMO; ++v)
-                    if (v >= L.nsig) h += Tg[k * NMO + v] * av[v];
-                av[k] = ainv[k] - h;
+            for (int v = 0; v < NMO; ++v) av[v] += ainv[k] * Cg[k * NMO + v];
+        }
+#pragma unroll
+        for (int v = 0; v < NMO; ++v) av[v] *= Sinv;
+        double h[JMAX];
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) {
+            h[k] = 0.0;
+            if (k < nmax) {
+#pragma unroll
+                for (int v = 0; v < NMO; ++v) h[k] += Tg[k * NMO + v] * av[v];
             }
         }
 #pragma unroll
-        for (int m = 0; m < NMO; ++m) {
-            gS0 += av[m] * double(mo[1][m]);
-            gS1 += av[m] * double(mo[2][m]);
-            gS2 += av[m] * double(mo[3][m]);
-            lapS += av[m] * double(mo[4][m]);
-        }
+        for (int k = 0; k < JMAX; ++k) av[k] = (k < L.nsig) ? ainv[k] - h[k] : av[k];
     }
+
+    // ---- pass 2: grad and Laplacian of Sigma at this electron ---------------
+    double gS0, gS1, gS2, lapS;
+    sigma_derivs<NMO, RT>(S, x0, x1, x2, av, gS0, gS1, gS2, lapS);
 
     // ---- local energy and log|Psi| ------------------------------------------
     double part = 0.0;
@@ -448,7 +512,7 @@ __global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__res
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * walker_lds_doubles(S, NMO);
+    double *wsm = smem + L.wloc * walker_lds<NMO>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -473,7 +537,7 @@ __global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__res
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * walker_lds_doubles(S, NMO);
+    double *wsm = smem + L.wloc * walker_lds<NMO>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -565,7 +629,7 @@ static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, d
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
                            uint32_t woff, double *ACC, hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
-    const size_t lds = (size_t)S.WPW * walker_lds_doubles(S, NMO) * sizeof(double);
+    const size_t lds = (size_t)S.WPW * walker_lds<NMO>(S) * sizeof(double);
     if (mc)
         hipLaunchKernelGGL((k_metropolis<NMO, RT>), dim3((unsigned)blocks), dim3(kWave), lds, st, S, X,
                            LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
