@@ -261,12 +261,13 @@ struct WalkerResult {
     double logpsi, sign, eloc;
 };
 
-// LDS of one walker: T tables [2][G][NMO], then a region shared by the
-// positions + pivot rows (before the determinant stage) and the cofactor
-// tables [2][G][NMO] (after it).
+// LDS of one walker: T tables [2][nmax][NMO] (nmax = max(n_up, n_dn)),
+// then a region shared by the positions + pivot rows (before the
+// determinant stage) and the cofactor tables [2][nmax][NMO] (after it).
 template <int NMO>
 __host__ __device__ inline int walker_lds(const DevSystem &S) {
-    const int t = 2 * S.G * NMO;
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int t = 2 * nmax * NMO;
     const int a = 3 * S.LW + 2 * NMO;
     return t + (a > t ? a : t);
 }
@@ -278,15 +279,16 @@ __host__ __device__ inline int walker_lds(const DevSystem &S) {
 template <int NMO, typename RT>
 __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
                                     double x1, double x2) {
-    double *sT = wsm;                        // [2][G][NMO]
-    double *sX = sT + 2 * S.G * NMO;         // shared region
-    double *sC = sX;                         // [2][G][NMO] after the elimination
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int tstride = nmax * NMO;          // doubles per spin table
+    double *sT = wsm;                        // [2][nmax][NMO]
+    double *sX = sT + 2 * tstride;           // shared region
+    double *sC = sX;                         // [2][nmax][NMO] after the elimination
     double *sPos = sX;                       // [LW][3] before it
     double *sPiv = sX + 3 * S.LW;            // [2][NMO] during it
-    double *Tg = sT + L.grp * S.G * NMO;
-    double *Cg = sC + L.grp * S.G * NMO;
+    double *Tg = sT + L.grp * tstride;
+    double *Cg = sC + L.grp * tstride;
     double *piv_row = sPiv + L.grp * NMO;
-    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
 
     if (!L.active) {  // a far point keeps idle lanes finite
         x0 = 100.0;
@@ -306,10 +308,12 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
             const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
             const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
             const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double rinv = 1.0 / r;
             const bool same = (j < S.n_up) == (L.e < S.n_up);
             const double a = same ? S.a_par : S.a_anti;
-            const double dinv = 1.0 / (1.0 + S.b * r);
+            // one division gives both 1/r and 1/(1 + b r)
+            const double den = 1.0 + S.b * r;
+            const double q = 1.0 / (r * den);
+            const double rinv = q * den, dinv = q * r;
             const double k1 = a * dinv * dinv;                      // K'(r)
             const double k2 = -2.0 * a * S.b * dinv * dinv * dinv;  // K''(r)
             J += 0.5 * a * r * dinv;
@@ -399,7 +403,7 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
     const double det_sign = ((inv_cnt & 1) ? -1.0 : 1.0) * (dprod < 0.0 ? -1.0 : 1.0);
     const double det_log = log(fabs(dprod));
     // the shared region now becomes the cofactor tables: zero them
-    for (int q = L.lw; q < 2 * S.G * NMO; q += S.LW) sC[q] = 0.0;
+    for (int q = L.lw; q < 2 * tstride; q += S.LW) sC[q] = 0.0;
     __syncthreads();
 
     const int wb = L.lane - L.lw;
@@ -408,7 +412,7 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
     const int sing_walker = walker_sum_i(singular ? 1 : 0, S.LW);
 
     // ---- S = sum_n d_n det T_up[H,P] det T_dn[H,P] ----------------------
-    const double *Tup = sT, *Tdn = sT + S.G * NMO;
+    const double *Tup = sT, *Tdn = sT + tstride;
     double Sp = 0.0;
     if (L.wvalid) {
         for (int n = L.lw; n < S.n_det; n += S.LW) {
@@ -433,7 +437,7 @@ __device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *w
                 const double cof = cb.y == 0 ? 1.0 : double(cb.y) * Ts[cb.z * NMO + cb.w];
                 val += S.ci[cb.x] * ratio<NMO>(To, d + oth) * cof;
             }
-            sC[en.x * S.G * NMO + en.y * NMO + en.z] = val;
+            sC[en.x * tstride + en.y * NMO + en.z] = val;
         }
     }
     __syncthreads();
@@ -570,7 +574,9 @@ __global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__res
         const double u0 = ((double)c[0] + 0.5) * s32, u1 = ((double)c[1] + 0.5) * s32;
         const double u2 = ((double)c[2] + 0.5) * s32, u3 = ((double)c[3] + 0.5) * s32;
         const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
-        const double z0 = r0 * cos(two_pi * u1), z1 = r0 * sin(two_pi * u1);
+        double s1, c1;
+        sincos(two_pi * u1, &s1, &c1);
+        const double z0 = r0 * c1, z1 = r0 * s1;
         const double z2 = r1 * cos(two_pi * u3);
         // no FMA contraction: X + sigma z rounds the product, then the sum
         const double y0 = __dadd_rn(x0, __dmul_rn(sigma, z0));
