@@ -47,11 +47,22 @@ typedef enum {
     QMC_EUNSUPPORTED = -4   /* valid input outside the compiled limits */
 } qmc_status;
 
-/* Arithmetic of a call.  QMC_FP64: everything in FP64.  QMC_MIXED_FP32 and
-   QMC_MIXED_BF16: AO values and the AO->MO contraction in reduced precision
-   (FP32 arithmetic; BF16 operands with FP32 accumulation), determinants,
-   Jacobi traces, Jastrow and E_L in FP64. */
-typedef enum { QMC_FP64 = 0, QMC_MIXED_FP32 = 1, QMC_MIXED_BF16 = 2 } qmc_precision;
+/* Arithmetic of a call.  QMC_FP64: everything in FP64.  The mixed forms
+   evaluate AO values in FP32 and keep the Slater inverse, determinant
+   ratios, Jacobi traces, Jastrow and E_L in FP64; they differ in the AO->MO
+   contractions:
+     QMC_MIXED_FP32     FP32 vector FMAs;
+     QMC_MIXED_BF16     BF16 matrix-core products with FP32 accumulation,
+                        each operand split into high and low BF16 parts
+                        (hi*hi + hi*lo + lo*hi, about 16 significant bits);
+     QMC_MIXED_BF16_X1  one BF16 product per pair (8 significant bits).
+   The BF16 forms need n_ao <= 32. */
+typedef enum {
+    QMC_FP64 = 0,
+    QMC_MIXED_FP32 = 1,
+    QMC_MIXED_BF16 = 2,
+    QMC_MIXED_BF16_X1 = 3
+} qmc_precision;
 
 /* Radial form of every AO: Slater r^kn exp(-zeta r) or contracted
    Gaussians sum_p c_p exp(-alpha_p r^2) (Methods, AO layer). */
@@ -118,12 +129,21 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
                                 double sigma, uint64_t seed, uint64_t step0,
                                 uint32_t walker_offset, double *d_acc, void *stream);
 
-/* Per-walker derivatives for the optimiser and forces (Methods, eqs.
-   nabla_loss and force): d log|Psi| / d theta [W][qmc_param_count] with
-   theta = (primitive exponents, MO coefficients, jas_b), and the nuclear
-   gradient d E_L / d R [W][n_atoms][3].  Either output may be NULL. */
+/* Per-walker derivatives for the optimiser and for forces, FP64 (Methods:
+   eq. nabla_loss needs d log|Psi| / d theta, eq. force needs d E_L / d R and
+   d ln rho / d R = 2 d log|Psi| / d R).  theta is laid out as
+   [primitive exponents in descriptor order | MO coefficients [n_ao][n_mo] in
+   the descriptor's layout | jas_b], qmc_param_count entries; the exponent
+   derivatives include the normalisation's dependence when normalize = 1.
+     d_dlogpsi      [W][P]  d log|Psi| / d theta
+     d_deloc_dtheta [W][P]  d E_L / d theta
+     d_dlogpsi_dR   [W][n_atoms][3]  d log|Psi| / d R_alpha
+     d_deloc_dR     [W][n_atoms][3]  d E_L / d R_alpha (includes V_nn)
+   Any output may be NULL; at least one must not be.  d_X as in
+   qmc_eval_psi_eloc.  Returns QMC_EUNSUPPORTED when the walker tables do not
+   fit the 160 KiB of LDS of a compute unit. */
 qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
-                    double *d_deloc_dR, void *stream);
+                    double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream);
 
 /* Number of variational parameters in the qmc_grad layout. */
 int64_t qmc_param_count(const qmc_system *sys);

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmc.so")
-SOURCES = ["qmc_api.hip", "qmc_kernels.hip"]
+SOURCES = ["qmc_api.hip", "qmc_kernels.hip", "qmc_grad.hip"]
 ARCH = os.environ.get("QMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -16,10 +16,14 @@
 #include <vector>
 
 namespace qmc {
-hipError_t launch_walkers(bool mc, bool fp32, const DevSystem &S, double *X, double *LP, double *SG,
+hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, double *LP, double *SG,
                           double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
                           uint64_t step0, uint32_t woff, double *ACC, hipStream_t st);
 int padded_mo(int n_mo);
+hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *dlogpsi,
+                       double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param,
+                       hipStream_t st);
+size_t grad_lds_bytes(const DevSystem &S);
 }  // namespace qmc
 
 using qmc::DevSystem;
@@ -171,6 +175,49 @@ qmc_status validate(const qmc_system_desc *d) {
     if (!is_finite(d->jas_a_par) || !is_finite(d->jas_a_anti) || !is_finite(d->jas_b) || d->jas_b < 0.0)
         return QMC_EINVAL;
     return QMC_OK;
+}
+
+uint16_t to_bf16(float f) {  // round to nearest even
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float from_bf16(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// Operand fragments of the matrix-core contractions: matrix 0 = C^T (rows
+// MOs, columns AOs), matrix 1 = C (rows AOs, columns MOs), both padded to
+// 32 x 32; fragment (tile t, lane l) holds M[16 t + l % 16][8 (l / 16) + e],
+// e = 0..7, as high and low BF16 parts.
+std::vector<uint4> mfma_fragments(const std::vector<double> &mo, int n_ao, int n_mo, int stride) {
+    std::vector<uint4> tab(2 * 2 * 2 * 64);
+    for (int mat = 0; mat < 2; ++mat)
+        for (int t = 0; t < 2; ++t)
+            for (int part = 0; part < 2; ++part)
+                for (int l = 0; l < 64; ++l) {
+                    uint16_t h[8];
+                    for (int e = 0; e < 8; ++e) {
+                        const int row = 16 * t + l % 16, col = 8 * (l / 16) + e;
+                        const int ao = mat == 0 ? col : row, m = mat == 0 ? row : col;
+                        const double x = (ao < n_ao && m < n_mo) ? mo[(size_t)ao * stride + m] : 0.0;
+                        const uint16_t hi = to_bf16((float)x);
+                        h[e] = part == 0 ? hi : to_bf16((float)(x - (double)from_bf16(hi)));
+                    }
+                    uint4 v;
+                    v.x = h[0] | ((uint32_t)h[1] << 16);
+                    v.y = h[2] | ((uint32_t)h[3] << 16);
+                    v.z = h[4] | ((uint32_t)h[5] << 16);
+                    v.w = h[6] | ((uint32_t)h[7] << 16);
+                    tab[((mat * 2 + t) * 2 + part) * 64 + l] = v;
+                }
+    return tab;
 }
 
 template <typename T>
@@ -330,6 +377,10 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     const size_t o_ci = push_bytes(blob, ci.data(), ci.size());
     const size_t o_ent = push_bytes(blob, entries.data(), entries.size());
     const size_t o_con = push_bytes(blob, contribs.data(), contribs.size());
+    const size_t o_perm = push_bytes(blob, old_of_new.data(), old_of_new.size());
+    const size_t o_angf = push_bytes(blob, angf.data(), angf.size());
+    const std::vector<uint4> frag = mfma_fragments(mo, n_ao, d->n_mo, nmo_pad);
+    const size_t o_frag = push_bytes(blob, frag.data(), frag.size());
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return QMC_EDEVICE;
@@ -365,6 +416,8 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.WPW = qmc::kWave / S.LW;
     S.nmo_pad = nmo_pad;
     S.basis = d->basis;
+    S.normalize = d->normalize;
+    S.n_prim = (int)prims.size();
     S.a_par = d->jas_a_par;
     S.a_anti = d->jas_a_anti;
     S.b = d->jas_b;
@@ -378,6 +431,9 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.ci = (const double *)(base + o_ci);
     S.entries = (const int4 *)(base + o_ent);
     S.contribs = (const int4 *)(base + o_con);
+    S.mo_perm = (const int *)(base + o_perm);
+    S.ao_angf = (const double *)(base + o_angf);
+    S.mfma_tab = (const uint4 *)(base + o_frag);
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
@@ -398,9 +454,9 @@ void qmc_system_destroy(qmc_system *sys) {
 static qmc_status check_walk_args(qmc_system *sys, int32_t precision, int64_t W) {
     if (!sys) return QMC_EINVAL;
     if (W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
-    if (precision != QMC_FP64 && precision != QMC_MIXED_FP32 && precision != QMC_MIXED_BF16)
-        return QMC_EINVAL;
-    if (precision == QMC_MIXED_BF16) return QMC_EUNSUPPORTED;
+    if (precision < QMC_FP64 || precision > QMC_MIXED_BF16_X1) return QMC_EINVAL;
+    if ((precision == QMC_MIXED_BF16 || precision == QMC_MIXED_BF16_X1) && sys->S.n_ao > 32)
+        return QMC_EUNSUPPORTED;
     return QMC_OK;
 }
 
@@ -412,7 +468,7 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
     if (!d_X || !d_logpsi || !d_sign || !d_eloc) return QMC_EINVAL;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
-    hipError_t e = qmc::launch_walkers(false, precision == QMC_MIXED_FP32, sys->S, (double *)d_X,
+    hipError_t e = qmc::launch_walkers(false, precision, sys->S, (double *)d_X,
                                        d_logpsi, d_sign, d_eloc, W, 0, 0.0, 0, 0, 0, nullptr,
                                        (hipStream_t)stream);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
@@ -430,20 +486,23 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
     if (!d_X || !d_logpsi || !d_sign || !d_eloc || !d_acc) return QMC_EINVAL;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
-    hipError_t e = qmc::launch_walkers(true, precision == QMC_MIXED_FP32, sys->S, d_X, d_logpsi,
+    hipError_t e = qmc::launch_walkers(true, precision, sys->S, d_X, d_logpsi,
                                        d_sign, d_eloc, W, n_steps, sigma, seed, step0, walker_offset,
                                        d_acc, (hipStream_t)stream);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 
 qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
-                    double *d_deloc_dR, void *stream) {
-    (void)d_X;
-    (void)d_dlogpsi;
-    (void)d_deloc_dR;
-    (void)stream;
-    if (!sys || W < 0) return QMC_EINVAL;
-    return QMC_EUNSUPPORTED;
+                    double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream) {
+    if (!sys || W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
+    if (W == 0) return QMC_OK;
+    if (!d_X || (!d_dlogpsi && !d_deloc_dtheta && !d_dlogpsi_dR && !d_deloc_dR)) return QMC_EINVAL;
+    if (qmc::grad_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
+    DeviceGuard g(sys->device);
+    if (!g.ok) return QMC_EDEVICE;
+    hipError_t e = qmc::launch_grad(sys->S, d_X, W, d_dlogpsi, d_deloc_dtheta, d_dlogpsi_dR, d_deloc_dR,
+                                    (int)sys->n_params, (hipStream_t)stream);
+    return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 
 int64_t qmc_param_count(const qmc_system *sys) { return sys ? sys->n_params : -1; }

@@ -23,6 +23,8 @@ struct DevSystem {
     int WPW;  // walkers per wave = 64 / LW
     int nmo_pad;  // row stride of the MO coefficient tables
     int basis;    // 0 Slater, 1 Gaussian
+    int normalize;  // 1: unit-normalised primitives (for exponent derivatives)
+    int n_prim;
     double a_par, a_anti, b, vnn;
     const double *atoms;    // [n_atoms][4]: x, y, z, Z
     const int4 *shells;     // [n_shells]: atom, l, kn, nprim
@@ -33,6 +35,11 @@ struct DevSystem {
     const double *ci;       // [n_det], canonicalisation signs folded in
     const int4 *entries;    // [n_entries + 1]: spin, slot k, MO v, first contribution
     const int4 *contribs;   // [n_contrib]: det, cofactor sign (0 = unit), h', p'
+    const int *mo_perm;     // [n_mo]: caller's column of each internal MO column
+    const double *ao_angf;  // [n_ao]: angular normalisation folded into the MO rows
+    // BF16 MFMA operand fragments [2 matrices: C^T, C][2 tiles][hi, lo][64 lanes],
+    // 8 bf16 each: lane l of tile t holds M[16 t + l % 16][8 (l / 16) + e].
+    const uint4 *mfma_tab;
 };
 
 }  // namespace qmc

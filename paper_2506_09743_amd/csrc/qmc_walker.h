@@ -1,0 +1,690 @@
+// Device-side building blocks of the walker evaluation, shared by the
+// evaluation / Metropolis kernels and the gradient kernel of libqmc.
+//
+// Work decomposition.  One wave of 64 lanes holds 64 / (2G) walkers; each
+// walker owns 2G consecutive lanes, G per spin, and lane i of a spin group
+// owns electron i of that spin.  A lane evaluates its electron's atomic
+// orbitals and molecular orbitals in registers, the Slater matrices are
+// factorised across the lanes of a group (row = electron), and the walker's
+// scalars are reduced across its lanes with cross-lane shuffles.  Walkers
+// never interact, so a walker's results do not depend on its neighbours.
+//
+// Kinetic energy (appendix on local energies).  With Psi = exp(J) Sigma the
+// Laplacian splits into lap J + |grad J|^2 + 2 grad J . grad Sigma / Sigma +
+// lap Sigma / Sigma.  Because every determinant is linear in the row of one
+// electron, grad_e Sigma / Sigma = sum_m a_e[m] grad phi_m(r_e) and
+// lap_e Sigma / Sigma = sum_m a_e[m] lap phi_m(r_e) with a_e[m] =
+// d log Sigma / d phi_m(r_e) (this is the per-electron Jacobi trace of
+// eq. claudia_trace summed over the CI expansion).  a_e follows from the
+// low-rank excited-determinant algebra of eq. table: with T = A0^-1 Phi,
+// every excited determinant is D0 det T[H,P] (k <= 2), Sigma = D0 S with
+// S = sum_n d_n det T_up[H,P] det T_dn[H,P], and the CI-weighted cofactors
+// C = dS/dT give a_e[v] = (A0^-T C)[e,v] / S on virtual orbitals and
+// a_e[k] = A0^-1[k,e] - (A0^-T C T^T)[e,k] / S on reference orbitals.
+// Only A0 is ever inverted, as in the paper's accelerated scheme.
+#pragma once
+
+#include "qmc_device.h"
+
+#include <math.h>
+
+namespace qmc {
+namespace walker {
+
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m); }
+
+// Sum over the LW lanes of a walker (LW a power of two, walkers aligned).
+__device__ __forceinline__ double walker_sum(double v, int LW) {
+    for (int off = 1; off < LW; off <<= 1) v += shfl_xor_d(v, off);
+    return v;
+}
+
+__device__ __forceinline__ int walker_sum_i(int v, int LW) {
+    for (int off = 1; off < LW; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+struct Lane {
+    int lane;    // 0..63
+    int wloc;    // walker slot in the wave
+    int lw;      // lane within walker, 0..LW-1
+    int grp;     // 0 spin up, 1 spin down
+    int i;       // index within the spin group
+    int e;       // electron index within the walker
+    int nsig;    // electrons of this spin
+    int gbase;   // first lane of the group
+    bool wvalid; // walker index < W
+    bool active; // owns a real electron of a valid walker
+};
+
+__device__ __forceinline__ Lane make_lane(const DevSystem &S, int64_t wave_first_walker, int64_t W,
+                                          int64_t *walker) {
+    Lane L;
+    L.lane = threadIdx.x;
+    L.wloc = L.lane / S.LW;
+    L.lw = L.lane % S.LW;
+    L.grp = L.lw / S.G;
+    L.i = L.lw % S.G;
+    L.nsig = L.grp == 0 ? S.n_up : S.n_dn;
+    L.e = L.grp == 0 ? L.i : S.n_up + L.i;
+    L.gbase = L.lane - L.i;
+    const int64_t w = wave_first_walker + L.wloc;
+    *walker = w;
+    L.wvalid = (L.wloc < S.WPW) && (w < W);
+    L.active = L.wvalid && (L.i < L.nsig);
+    return L;
+}
+
+// Determinant ratio det T[H,P] of one spin, rank k <= 2, from the walker's
+// T table (row = slot, column = MO, stride NMO).
+template <int NMO>
+__device__ __forceinline__ double ratio(const double *T, const int *d) {
+    const int k = d[0];
+    if (k == 0) return 1.0;
+    const double a = T[d[1] * NMO + d[3]];
+    if (k == 1) return a;
+    return a * T[d[2] * NMO + d[4]] - T[d[1] * NMO + d[4]] * T[d[2] * NMO + d[3]];
+}
+
+template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
+template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
+
+template <typename RT> __device__ __forceinline__ const RT *mo_table(const DevSystem &S);
+template <> __device__ __forceinline__ const double *mo_table<double>(const DevSystem &S) { return S.mo; }
+template <> __device__ __forceinline__ const float *mo_table<float>(const DevSystem &S) { return S.mo_f; }
+
+// Radial part of one shell at distance r: R, and with DERIV also R'/r and
+// R'' + (2l+2) R'/r.  Slater R = sum_p c_p r^kn exp(-zeta_p r), so R'/R =
+// kn/r - zeta; Gaussian R = sum_p c_p exp(-alpha_p r^2), so R'/r = -2 alpha R
+// and R'' + (2l+2) R'/r = (4 alpha^2 r^2 - (4l+6) alpha) R.  The primitive
+// coefficients carry the radial normalisation.
+template <typename RT, bool DERIV>
+__device__ __forceinline__ void shell_radial(const DevSystem &S, int p, int np, int l, int kn, RT r,
+                                             RT r2, RT rinv, RT &Rv, RT &Rd, RT &Rl) {
+    Rv = RT(0);
+    Rd = RT(0);
+    Rl = RT(0);
+    if (S.basis == 0) {
+        const RT fl = RT(2 * l + 2);
+        RT rk = RT(1);
+        for (int t = 0; t < kn; ++t) rk *= r;
+        for (int q = 0; q < np; ++q) {
+            const double2 pe = S.prims[p + q];
+            const RT ex = RT(pe.x);
+            const RT f = RT(pe.y) * rk * rt_exp<RT>(-ex * r);
+            Rv += f;
+            if (DERIV) {
+                const RT g = RT(kn) * rinv - ex;
+                Rd += f * g * rinv;
+                Rl += f * (g * g - RT(kn) * rinv * rinv + fl * g * rinv);
+            }
+        }
+    } else {
+        const RT fl = RT(4 * l + 6);
+        for (int q = 0; q < np; ++q) {
+            const double2 pe = S.prims[p + q];
+            const RT ex = RT(pe.x);
+            const RT f = RT(pe.y) * rt_exp<RT>(-ex * r2);
+            Rv += f;
+            if (DERIV) {
+                Rd -= RT(2) * ex * f;
+                Rl += f * (RT(4) * ex * ex * r2 - fl * ex);
+            }
+        }
+    }
+}
+
+// Pass 1: MO values phi_m(r_e) = sum_mu C[mu][m] chi_mu(r_e) of the lane's
+// electron (Methods, AO and MO layers).  AO = P(x,y,z) R(r) with P a
+// Cartesian monomial; angular normalisations are folded into the rows of C.
+template <int NMO, typename RT>
+__device__ __forceinline__ void mo_values(const DevSystem &S, double x0, double x1, double x2,
+                                          RT (&phi)[NMO]) {
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) phi[m] = RT(0);
+    const RT *C = mo_table<RT>(S);
+    int p = 0;
+    const RT *crow = C;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        // displacement in FP64, cast afterwards
+        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
+        const RT r2 = dx * dx + dy * dy + dz * dz;
+        const RT r = sqrt(r2);
+        RT Rv, Rd, Rl;
+        shell_radial<RT, false>(S, p, si.w, si.y, si.z, r, r2, RT(0), Rv, Rd, Rl);
+        p += si.w;
+        const int nc = (si.y + 1) * (si.y + 2) / 2;
+        for (int c = 0; c < nc; ++c) {
+            RT P;
+            if (si.y == 0) P = RT(1);
+            else if (si.y == 1) P = c == 0 ? dx : (c == 1 ? dy : dz);
+            else {
+                const RT u = (c < 3) ? dx : (c < 5 ? dy : dz);
+                const RT v = (c == 0) ? dx : (c == 1 || c == 3) ? dy : dz;
+                P = u * v;
+            }
+            const RT val = P * Rv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) phi[m] += val * crow[m];
+            crow += S.nmo_pad;
+        }
+    }
+}
+
+// Pass 2: grad_e Sigma / Sigma and lap_e Sigma / Sigma.  With a_e[m] =
+// d log Sigma / d phi_m(r_e) and t_mu = sum_m C[mu][m] a_e[m], both are
+// sum_mu t_mu (grad, lap) chi_mu(r_e); for chi = P R:
+//   grad chi = R grad P + P (R'/r) d,   lap chi = R lap P + P (R'' + (2l+2) R'/r).
+template <int NMO, typename RT>
+__device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, double x1, double x2,
+                                             const double (&av)[NMO], double &g0, double &g1,
+                                             double &g2, double &lap) {
+    const RT *C = mo_table<RT>(S);
+    RT a[NMO];
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) a[m] = RT(av[m]);
+    int p = 0;
+    const RT *crow = C;
+    double G0 = 0.0, G1 = 0.0, G2 = 0.0, L = 0.0;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
+        const RT r2 = dx * dx + dy * dy + dz * dz;
+        const RT r = sqrt(r2);
+        const RT rinv = RT(1) / r;
+        RT Rv, Rd, Rl;
+        shell_radial<RT, true>(S, p, si.w, si.y, si.z, r, r2, rinv, Rv, Rd, Rl);
+        p += si.w;
+        const int nc = (si.y + 1) * (si.y + 2) / 2;
+        for (int c = 0; c < nc; ++c) {
+            RT t = RT(0);
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) t += crow[m] * a[m];
+            crow += S.nmo_pad;
+            // monomial, its gradient and Laplacian
+            RT P, Px, Py, Pz, PL;
+            if (si.y == 0) {
+                P = RT(1); Px = Py = Pz = PL = RT(0);
+            } else if (si.y == 1) {
+                P = c == 0 ? dx : (c == 1 ? dy : dz);
+                Px = c == 0 ? RT(1) : RT(0);
+                Py = c == 1 ? RT(1) : RT(0);
+                Pz = c == 2 ? RT(1) : RT(0);
+                PL = RT(0);
+            } else {
+                // xx, xy, xz, yy, yz, zz
+                const int iu = (c < 3) ? 0 : (c < 5 ? 1 : 2);
+                const int iv = (c == 0) ? 0 : (c == 1 || c == 3) ? 1 : 2;
+                const RT u = iu == 0 ? dx : (iu == 1 ? dy : dz);
+                const RT v = iv == 0 ? dx : (iv == 1 ? dy : dz);
+                P = u * v;
+                Px = (iu == 0 ? v : RT(0)) + (iv == 0 ? u : RT(0));
+                Py = (iu == 1 ? v : RT(0)) + (iv == 1 ? u : RT(0));
+                Pz = (iu == 2 ? v : RT(0)) + (iv == 2 ? u : RT(0));
+                PL = iu == iv ? RT(2) : RT(0);
+            }
+            const RT PRd = P * Rd;
+            G0 += double(t * (Rv * Px + PRd * dx));
+            G1 += double(t * (Rv * Py + PRd * dy));
+            G2 += double(t * (Rv * Pz + PRd * dz));
+            L += double(t * (Rv * PL + P * Rl));
+        }
+    }
+    g0 = G0;
+    g1 = G1;
+    g2 = G2;
+    lap = L;
+}
+
+// ---- BF16 matrix-core contractions (mixed form) ------------------------------
+// A wave applies a fixed 32 x 32 matrix M (C^T for MO values, C for the AO
+// weights t = C a_e) to one 32-vector per lane with v_mfma_f32_16x16x32_bf16:
+// output tile t (16 rows of M) times the vectors of lane quarter q (16 lanes)
+// is one MFMA.  Vectors are staged through LDS so that lane 16 g + j supplies
+// elements 8 g .. 8 g + 7 of lane 16 q + j's vector; the 16 x 16 result lands
+// as rows 4 g .. 4 g + 3 in lane 16 g + j and goes back through LDS to the
+// lane that owns the vector.  SPLIT = 3 writes every operand as a sum of a
+// high and a low BF16 part and forms hi*hi + hi*lo + lo*hi (about 16
+// significant bits); SPLIT = 1 uses the high parts only.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+constexpr int kStageK = 32;      // padded vector length
+constexpr int kRowB = 40;        // bf16 per staged row (80 B, 16-byte aligned)
+constexpr int kRowF = 36;        // floats per result row (144 B)
+constexpr int kStageBytes = 2 * kWave * kRowB * 2 + kWave * kRowF * 4;
+
+struct Stage {
+    __bf16 *hi, *lo;  // [64][kRowB]
+    float *out;       // [64][kRowF]
+};
+
+__device__ __forceinline__ Stage make_stage(void *base) {
+    Stage st;
+    st.hi = (__bf16 *)base;
+    st.lo = st.hi + kWave * kRowB;
+    st.out = (float *)(st.lo + kWave * kRowB);
+    return st;
+}
+
+__device__ __forceinline__ void stage_put(const Stage &st, int lane, int k, float v) {
+    const __bf16 h = (__bf16)v;
+    st.hi[lane * kRowB + k] = h;
+    st.lo[lane * kRowB + k] = (__bf16)(v - (float)h);
+}
+
+// out[lane][o] = sum_k M[o][k] v_lane[k] for o < 16 NT (M = matrix mat).
+template <int NT, int SPLIT>
+__device__ __forceinline__ void mfma_apply(const DevSystem &S, int mat, const Stage &st, int lane) {
+    const int g = lane >> 4, j = lane & 15;
+    bf16x8_t ahi[NT], alo[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const uint4 h = S.mfma_tab[((mat * 2 + t) * 2 + 0) * kWave + lane];
+        const uint4 l = S.mfma_tab[((mat * 2 + t) * 2 + 1) * kWave + lane];
+        ahi[t] = __builtin_bit_cast(bf16x8_t, h);
+        alo[t] = __builtin_bit_cast(bf16x8_t, l);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int src = (16 * q + j) * kRowB + 8 * g;
+        const bf16x8_t bh = *(const bf16x8_t *)(st.hi + src);
+        const bf16x8_t bl = *(const bf16x8_t *)(st.lo + src);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[t], bh, acc, 0, 0, 0);
+            if (SPLIT == 3) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[t], bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[t], bh, acc, 0, 0, 0);
+            }
+            *(floatx4_t *)(st.out + (16 * q + j) * kRowF + 16 * t + 4 * g) = acc;
+        }
+    }
+}
+
+// Pass 1 on the matrix cores: AO values in FP32, staged as BF16 parts, MO
+// values phi[m] = sum_mu C[mu][m] chi_mu with FP32 accumulation.  Every lane
+// of the wave must call it.
+template <int NMO, int SPLIT>
+__device__ __forceinline__ void mo_values_mfma(const DevSystem &S, int lane, void *stage_base, double x0,
+                                               double x1, double x2, float (&phi)[NMO]) {
+    const Stage st = make_stage(stage_base);
+    int p = 0, mu = 0;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        const float dx = float(x0 - A[0]), dy = float(x1 - A[1]), dz = float(x2 - A[2]);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float r = sqrtf(r2);
+        float Rv, Rd, Rl;
+        shell_radial<float, false>(S, p, si.w, si.y, si.z, r, r2, 0.f, Rv, Rd, Rl);
+        p += si.w;
+        const int nc = (si.y + 1) * (si.y + 2) / 2;
+        for (int c = 0; c < nc; ++c, ++mu) {
+            float P;
+            if (si.y == 0) P = 1.f;
+            else if (si.y == 1) P = c == 0 ? dx : (c == 1 ? dy : dz);
+            else {
+                const float u = (c < 3) ? dx : (c < 5 ? dy : dz);
+                const float v = (c == 0) ? dx : (c == 1 || c == 3) ? dy : dz;
+                P = u * v;
+            }
+            stage_put(st, lane, mu, P * Rv);
+        }
+    }
+    for (int k = mu; k < kStageK; ++k) stage_put(st, lane, k, 0.f);
+    __syncthreads();
+    mfma_apply<(NMO + 15) / 16, SPLIT>(S, 0, st, lane);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) phi[m] = st.out[lane * kRowF + m];
+    __syncthreads();
+}
+
+// AO weights t_mu = sum_m C[mu][m] a_e[m] of every lane on the matrix cores;
+// on return st.out[lane][mu] holds them (read before the next staging).
+template <int NMO, int SPLIT>
+__device__ __forceinline__ void ao_weights_mfma(const DevSystem &S, int lane, void *stage_base,
+                                                const double (&av)[NMO]) {
+    const Stage st = make_stage(stage_base);
+    __syncthreads();  // the staging area overlays the T and cofactor tables
+#pragma unroll
+    for (int m = 0; m < kStageK; ++m) stage_put(st, lane, m, m < NMO ? float(av[m < NMO ? m : 0]) : 0.f);
+    __syncthreads();
+    mfma_apply<2, SPLIT>(S, 1, st, lane);
+    __syncthreads();
+}
+
+// Pass 2 with precomputed AO weights t (float, LDS row of this lane).
+template <typename RT>
+__device__ __forceinline__ void sigma_derivs_t(const DevSystem &S, double x0, double x1, double x2,
+                                               const float *t_row, double &g0, double &g1, double &g2,
+                                               double &lap) {
+    int p = 0, mu = 0;
+    double G0 = 0.0, G1 = 0.0, G2 = 0.0, Lp = 0.0;
+    for (int sh = 0; sh < S.n_shells; ++sh) {
+        const int4 si = S.shells[sh];
+        const double *A = S.atoms + 4 * si.x;
+        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
+        const RT r2 = dx * dx + dy * dy + dz * dz;
+        const RT r = sqrt(r2);
+        const RT rinv = RT(1) / r;
+        RT Rv, Rd, Rl;
+        shell_radial<RT, true>(S, p, si.w, si.y, si.z, r, r2, rinv, Rv, Rd, Rl);
+        p += si.w;
+        const int nc = (si.y + 1) * (si.y + 2) / 2;
+        for (int c = 0; c < nc; ++c, ++mu) {
+            const RT t = RT(t_row[mu]);
+            RT P, Px, Py, Pz, PL;
+            if (si.y == 0) {
+                P = RT(1); Px = Py = Pz = PL = RT(0);
+            } else if (si.y == 1) {
+                P = c == 0 ? dx : (c == 1 ? dy : dz);
+                Px = c == 0 ? RT(1) : RT(0);
+                Py = c == 1 ? RT(1) : RT(0);
+                Pz = c == 2 ? RT(1) : RT(0);
+                PL = RT(0);
+            } else {
+                const int iu = (c < 3) ? 0 : (c < 5 ? 1 : 2);
+                const int iv = (c == 0) ? 0 : (c == 1 || c == 3) ? 1 : 2;
+                const RT u = iu == 0 ? dx : (iu == 1 ? dy : dz);
+                const RT v = iv == 0 ? dx : (iv == 1 ? dy : dz);
+                P = u * v;
+                Px = (iu == 0 ? v : RT(0)) + (iv == 0 ? u : RT(0));
+                Py = (iu == 1 ? v : RT(0)) + (iv == 1 ? u : RT(0));
+                Pz = (iu == 2 ? v : RT(0)) + (iv == 2 ? u : RT(0));
+                PL = iu == iv ? RT(2) : RT(0);
+            }
+            const RT PRd = P * Rd;
+            G0 += double(t * (Rv * Px + PRd * dx));
+            G1 += double(t * (Rv * Py + PRd * dy));
+            G2 += double(t * (Rv * Pz + PRd * dz));
+            Lp += double(t * (Rv * PL + P * Rl));
+        }
+    }
+    g0 = G0;
+    g1 = G1;
+    g2 = G2;
+    lap = Lp;
+}
+
+// LDS of one walker: T tables [2][nmax][NMO] (nmax = max(n_up, n_dn)),
+// then a region shared by the positions + pivot rows (before the
+// determinant stage) and the cofactor tables [2][nmax][NMO] (after it).
+template <int NMO>
+__host__ __device__ inline int walker_lds(const DevSystem &S) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int t = 2 * nmax * NMO;
+    const int a = 3 * S.LW + 2 * NMO;
+    return t + (a > t ? a : t);
+}
+
+// Per-lane results of the stages every evaluation shares.
+template <int NMO>
+struct Core {
+    double J, gJ0, gJ1, gJ2, lapJ, vpot;  // this electron's Jastrow and Coulomb terms
+    int slot;                             // Gauss-Jordan slot of this electron
+    double Ssum, logD_up, logD_dn, sgn_up, sgn_dn;
+    int sing_walker;                      // > 0: a reference matrix is exactly singular
+    double av[NMO];                       // a_e[m] = d log Sigma / d phi_m(r_e)
+};
+
+// Jastrow and Coulomb terms, pass 1 (MO values), in-place Gauss-Jordan of
+// the reference matrices, determinant ratios, S, cofactor tables and the
+// adjoint vector a_e.  Every lane of the block must call it (it contains
+// block barriers).  On return the walker's LDS holds the T tables
+// [2][nmax][NMO] at wsm and the cofactor tables right after them.
+template <int NMO, typename RT, int MF = 0>
+__device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
+                                            double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int tstride = nmax * NMO;          // doubles per spin table
+    double *sT = wsm;                        // [2][nmax][NMO]
+    double *sX = sT + 2 * tstride;           // shared region
+    double *sC = sX;                         // [2][nmax][NMO] after the elimination
+    double *sPos = sX;                       // [LW][3] before it
+    double *sPiv = sX + 3 * S.LW;            // [2][NMO] during it
+    double *Tg = sT + L.grp * tstride;
+    double *Cg = sC + L.grp * tstride;
+    double *piv_row = sPiv + L.grp * NMO;
+
+    if (!L.active) {  // a far point keeps idle lanes finite
+        x0 = 100.0;
+        x1 = 100.0;
+        x2 = 100.0;
+    }
+    sPos[3 * L.lw + 0] = x0;
+    sPos[3 * L.lw + 1] = x1;
+    sPos[3 * L.lw + 2] = x2;
+    __syncthreads();
+
+    // ---- Pade e-e Jastrow and Coulomb terms of this electron -------------
+    double J = 0.0, gJ0 = 0.0, gJ1 = 0.0, gJ2 = 0.0, lapJ = 0.0, vpot = 0.0;
+    if (L.active) {
+        for (int j = 0; j < S.ne; ++j) {
+            if (j == L.e) continue;
+            const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
+            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const bool same = (j < S.n_up) == (L.e < S.n_up);
+            const double a = same ? S.a_par : S.a_anti;
+            // one division gives both 1/r and 1/(1 + b r)
+            const double den = 1.0 + S.b * r;
+            const double q = 1.0 / (r * den);
+            const double rinv = q * den, dinv = q * r;
+            const double k1 = a * dinv * dinv;                      // K'(r)
+            const double k2 = -2.0 * a * S.b * dinv * dinv * dinv;  // K''(r)
+            J += 0.5 * a * r * dinv;
+            gJ0 += k1 * d0 * rinv;
+            gJ1 += k1 * d1 * rinv;
+            gJ2 += k1 * d2 * rinv;
+            lapJ += k2 + 2.0 * k1 * rinv;
+            vpot += 0.5 * rinv;
+        }
+        for (int a = 0; a < S.n_atoms; ++a) {
+            const double *A = S.atoms + 4 * a;
+            const double d0 = x0 - A[0], d1 = x1 - A[1], d2 = x2 - A[2];
+            vpot -= A[3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+    }
+
+    // ---- pass 1: MO values of this electron ------------------------------
+    double a[NMO];
+    if constexpr (MF > 0) {
+        // the staging area overlays the walkers' tables: wait for the
+        // position reads of the pair loop first
+        __syncthreads();
+        float phi[NMO];
+        mo_values_mfma<NMO, MF>(S, L.lane, stage, x0, x1, x2, phi);
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) a[m] = double(phi[m]);
+    } else {
+        RT phi[NMO];
+        mo_values<NMO, RT>(S, x0, x1, x2, phi);
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) a[m] = double(phi[m]);
+    }
+
+    // ---- in-place Gauss-Jordan of the reference matrix across the group --
+    // Row = this electron's MO values.  Pivot column j (reference orbital j
+    // after the create-time column permutation) is overwritten by the
+    // inverse, so at the end the row of slot s holds A0^-1[s][slot(e)] in
+    // the columns < n and T[s][v] = (A0^-1 Phi)[s][v] in the virtual columns.
+    constexpr int JMAX = kMaxSpin < NMO ? kMaxSpin : NMO;
+    bool done = !L.active;
+    int slot = -1;
+    double dprod = 1.0;
+    bool singular = false;
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        if (j >= nmax) break;
+        const bool work = j < L.nsig;
+        double cand = (work && !done) ? fabs(a[j]) : -1.0;
+        int cl = L.i;
+        for (int off = 1; off < S.G; off <<= 1) {
+            const double oc = shfl_xor_d(cand, off);
+            const int ol = __shfl_xor(cl, off);
+            if (oc > cand || (oc == cand && ol < cl)) {
+                cand = oc;
+                cl = ol;
+            }
+        }
+        const double piv = __shfl(a[j], L.gbase + cl);
+        const bool ok = work && cand > 0.0;
+        if (work && !ok) singular = true;
+        const bool is_piv = ok && L.active && L.i == cl;
+        if (is_piv) {
+            // publish the unscaled pivot row, then scale this row in place
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) piv_row[m] = a[m];
+            const double inv = 1.0 / piv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) a[m] *= inv;
+            a[j] = inv;
+            done = true;
+            slot = j;
+        }
+        if (work) dprod *= piv;
+        __syncthreads();
+        if (ok && L.active && !is_piv) {
+            // multiplier as in Doolittle elimination: equal rows cancel exactly
+            const double f = a[j] / piv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) a[m] -= f * piv_row[m];
+            a[j] = -f;
+        }
+        __syncthreads();
+    }
+    if (L.active && slot >= 0) {
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) Tg[slot * NMO + m] = a[m];
+    }
+    // Permutation parity (slot s <- electron row): inversions within the group.
+    int inv_cnt = 0;
+    for (int ip = 0; ip < S.G; ++ip) {
+        const int so = __shfl(slot, L.gbase + ip);
+        if (L.active && ip > L.i && so >= 0 && so < slot) ++inv_cnt;
+    }
+    for (int off = 1; off < S.G; off <<= 1) inv_cnt += __shfl_xor(inv_cnt, off);
+    const double det_sign = ((inv_cnt & 1) ? -1.0 : 1.0) * (dprod < 0.0 ? -1.0 : 1.0);
+    const double det_log = log(fabs(dprod));
+    // the shared region now becomes the cofactor tables: zero them
+    for (int q = L.lw; q < 2 * tstride; q += S.LW) sC[q] = 0.0;
+    __syncthreads();
+
+    const int wb = L.lane - L.lw;
+    const double logD_up = __shfl(det_log, wb), logD_dn = __shfl(det_log, wb + S.G);
+    const double sgn_up = __shfl(det_sign, wb), sgn_dn = __shfl(det_sign, wb + S.G);
+    const int sing_walker = walker_sum_i(singular ? 1 : 0, S.LW);
+
+    // ---- S = sum_n d_n det T_up[H,P] det T_dn[H,P] ----------------------
+    const double *Tup = sT, *Tdn = sT + tstride;
+    double Sp = 0.0;
+    if (L.wvalid) {
+        for (int n = L.lw; n < S.n_det; n += S.LW) {
+            const int *d = S.dets + n * kDetInts;
+            Sp += S.ci[n] * ratio<NMO>(Tup, d) * ratio<NMO>(Tdn, d + 5);
+        }
+    }
+    const double Ssum = walker_sum(Sp, S.LW);
+
+    // ---- cofactor tables C_sigma[k][v] = dS / dT_sigma[k][v] ---------------
+    if (L.wvalid) {
+        for (int t = L.lw; t < S.n_entries; t += S.LW) {
+            const int4 en = S.entries[t];
+            const int end = S.entries[t + 1].w;
+            const double *Ts = en.x == 0 ? Tup : Tdn;
+            const double *To = en.x == 0 ? Tdn : Tup;
+            const int oth = en.x == 0 ? 5 : 0;
+            double val = 0.0;
+            for (int c = en.w; c < end; ++c) {
+                const int4 cb = S.contribs[c];
+                const int *d = S.dets + cb.x * kDetInts;
+                const double cof = cb.y == 0 ? 1.0 : double(cb.y) * Ts[cb.z * NMO + cb.w];
+                val += S.ci[cb.x] * ratio<NMO>(To, d + oth) * cof;
+            }
+            sC[en.x * tstride + en.y * NMO + en.z] = val;
+        }
+    }
+    __syncthreads();
+
+    // ---- a_e = d log Sigma / d phi(r_e) ------------------------------------
+    // virtual orbitals: a_e[v] = (A0^-T C)[e][v] / S (C vanishes on the
+    // reference columns); reference orbitals: a_e[k] = A0^-1[k][e] -
+    // sum_v T[k][v] a_e[v].
+    double (&av)[NMO] = c.av;
+    {
+        const int sl = slot < 0 ? 0 : slot;
+        double ainv[JMAX];
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) {
+            ainv[k] = 0.0;
+            if (k < nmax) {
+                const double t = Tg[k * NMO + sl];
+                ainv[k] = (k < L.nsig && L.active) ? t : 0.0;
+            }
+        }
+        const double Sinv = 1.0 / Ssum;
+#pragma unroll
+        for (int v = 0; v < NMO; ++v) av[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) {
+            if (k >= nmax) break;
+#pragma unroll
+            for (int v = 0; v < NMO; ++v) av[v] += ainv[k] * Cg[k * NMO + v];
+        }
+#pragma unroll
+        for (int v = 0; v < NMO; ++v) av[v] *= Sinv;
+        double h[JMAX];
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) {
+            h[k] = 0.0;
+            if (k < nmax) {
+#pragma unroll
+                for (int v = 0; v < NMO; ++v) h[k] += Tg[k * NMO + v] * av[v];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) av[k] = (k < L.nsig) ? ainv[k] - h[k] : av[k];
+    }
+
+    c.J = J;
+    c.gJ0 = gJ0;
+    c.gJ1 = gJ1;
+    c.gJ2 = gJ2;
+    c.lapJ = lapJ;
+    c.vpot = vpot;
+    c.slot = slot;
+    c.Ssum = Ssum;
+    c.logD_up = logD_up;
+    c.logD_dn = logD_dn;
+    c.sgn_up = sgn_up;
+    c.sgn_dn = sgn_dn;
+    c.sing_walker = sing_walker;
+}
+
+}  // namespace walker
+}  // namespace qmc

@@ -16,9 +16,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
 QMC_OK, QMC_EINVAL, QMC_ENOMEM, QMC_EDEVICE, QMC_EUNSUPPORTED = 0, -1, -2, -3, -4
-QMC_FP64, QMC_MIXED_FP32, QMC_MIXED_BF16 = 0, 1, 2
+QMC_FP64, QMC_MIXED_FP32, QMC_MIXED_BF16, QMC_MIXED_BF16_X1 = 0, 1, 2, 3
 QMC_STO, QMC_GTO = 0, 1
-PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_MIXED_FP32, "bf16": QMC_MIXED_BF16}
+PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_MIXED_FP32, "bf16": QMC_MIXED_BF16,
+              "bf16x1": QMC_MIXED_BF16_X1}
 
 # every symbol include/qmc.h declares
 EXPORTS = ("qmc_system_create", "qmc_system_destroy", "qmc_eval_psi_eloc", "qmc_metropolis_block",
@@ -68,7 +69,8 @@ def lib():
                                            C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64,
                                            C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p]
         L.qmc_metropolis_block.restype = C.c_int
-        L.qmc_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.qmc_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p]
         L.qmc_grad.restype = C.c_int
         L.qmc_param_count.argtypes = [C.c_void_p]
         L.qmc_param_count.restype = C.c_int64
@@ -173,12 +175,15 @@ def qmc_metropolis_block(handle, precision: int, X, logpsi, sign, eloc, n_steps:
                                       _dev_ptr(acc, "acc", (W, 3)), _stream()), "qmc_metropolis_block")
 
 
-def qmc_grad(handle, X, dlogpsi=None, deloc_dR=None) -> None:
+def qmc_grad(handle, X, dlogpsi=None, deloc_dtheta=None, dlogpsi_dR=None, deloc_dR=None) -> None:
     W = X.shape[0]
-    _check(lib().qmc_grad(handle, _dev_ptr(X, "X"), W,
-                          _dev_ptr(dlogpsi, "dlogpsi") if dlogpsi is not None else None,
-                          _dev_ptr(deloc_dR, "deloc_dR") if deloc_dR is not None else None,
-                          _stream()), "qmc_grad")
+
+    def opt(t, name):
+        return _dev_ptr(t, name) if t is not None else None
+
+    _check(lib().qmc_grad(handle, _dev_ptr(X, "X"), W, opt(dlogpsi, "dlogpsi"),
+                          opt(deloc_dtheta, "deloc_dtheta"), opt(dlogpsi_dR, "dlogpsi_dR"),
+                          opt(deloc_dR, "deloc_dR"), _stream()), "qmc_grad")
 
 
 def qmc_param_count(handle) -> int:
@@ -224,6 +229,18 @@ class System:
         W = X.shape[0]
         out = [torch.empty(W, dtype=torch.float64, device=X.device) for _ in range(3)]
         qmc_eval_psi_eloc(self.handle, PRECISIONS[precision], X, *out)
+        return tuple(out)
+
+    def grad(self, X):
+        """(d log|Psi|/d theta [W,P], d E_L/d theta [W,P], d log|Psi|/d R [W,A,3],
+        d E_L/d R [W,A,3]) in FP64."""
+        import torch
+        W, P, A = X.shape[0], self.param_count, self.n_atoms
+        out = [torch.empty((W, P), dtype=torch.float64, device=X.device),
+               torch.empty((W, P), dtype=torch.float64, device=X.device),
+               torch.empty((W, A, 3), dtype=torch.float64, device=X.device),
+               torch.empty((W, A, 3), dtype=torch.float64, device=X.device)]
+        qmc_grad(self.handle, X, *out)
         return tuple(out)
 
     def metropolis(self, X, logpsi, sign, eloc, n_steps, sigma, seed, step0=0, walker_offset=0,

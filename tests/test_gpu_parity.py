@@ -301,20 +301,40 @@ def test_abi_rejects_bad_arguments(torch_cuda, qmc):
         qmc.System(synth.make_system("CO"), device=99)
 
 
-@pytest.mark.parametrize("name", ["LiH", "CO"])
-def test_mixed_fp32_error(torch_cuda, qmc, oracle_mod, name):
-    """Mixed form (FP32 AOs and MO contraction, FP64 elsewhere): per-walker
-    E_L error and mean-energy error against the oracle, reported and bounded
-    loosely (this is a precision study, not an FP64 parity check)."""
+@pytest.mark.parametrize("name,prec,med_tol", [("LiH", "fp32", 1e-4), ("CO", "fp32", 1e-4),
+                                               ("LiH", "bf16", 1e-3), ("CO", "bf16", 1e-3),
+                                               ("CO", "bf16x1", 1e-1)])
+def test_mixed_error(torch_cuda, qmc, oracle_mod, name, prec, med_tol):
+    """Mixed forms (FP32 AOs; MO contractions in FP32 or on BF16 matrix
+    cores; FP64 elsewhere): per-walker E_L error and mean-energy error
+    against the oracle, reported and bounded loosely (a precision study,
+    not an FP64 parity check)."""
     torch = torch_cuda
     sysd = synth.make_system(name)
     X = synth.init_walkers(sysd, 512, 12)
     s = _gpu_system(qmc, name)
-    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision="fp32")]
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
     rlp, rsg, rel = oracle_mod.OracleSystem(sysd).eval(X)
     de = np.abs(el - rel)
     rel_err = de / np.maximum(1.0, np.abs(rel))
-    print(f"{name} mixed fp32: median |dE_L| {np.median(de):.2e} p99 {np.quantile(de, 0.99):.2e} "
+    print(f"{name} mixed {prec}: median |dE_L| {np.median(de):.2e} p99 {np.quantile(de, 0.99):.2e} "
           f"mean-energy err {abs(el.mean() - rel.mean()):.2e}")
-    assert np.median(rel_err) < 1e-4
-    assert np.mean(sg == rsg) > 0.99
+    assert np.median(rel_err) < med_tol
+    assert np.mean(sg == rsg) > (0.99 if prec != "bf16x1" else 0.8)
+
+
+def test_mixed_bf16_metropolis_runs(torch_cuda, qmc):
+    """The matrix-core form inside the Metropolis block: same acceptance
+    statistics as FP64 on the same stream, within a few percent."""
+    torch = torch_cuda
+    sysd = synth.make_system("CO")
+    s = _gpu_system(qmc, "CO")
+    X0 = torch.from_numpy(synth.init_walkers(sysd, 1024, 9)).cuda()
+    out = {}
+    for prec in ("fp64", "bf16"):
+        X = X0.clone()
+        lp, sg, el = s.eval(X, precision=prec)
+        acc = s.metropolis(X, lp, sg, el, 20, 0.2, 77, precision=prec)
+        out[prec] = acc.cpu().numpy()
+    a64, a16 = out["fp64"][:, 2].mean(), out["bf16"][:, 2].mean()
+    assert abs(a64 - a16) < 0.05 * max(a64, 0.05), (a64, a16)
