@@ -8,8 +8,10 @@ walker state stays in HBM between blocks.  The timed region starts from an
 equilibrated state (burn-in) with all inputs resident on the device.
 
 Prints one JSON line (see the keys below).  The FP64 form is `value`; the
-mixed FP32 form (FP32 AOs and MO contraction, FP64 determinants and E_L) is
-reported beside it with its energy errors.
+mixed forms are reported beside it with their energy errors against the FP64
+oracle: FP32 (FP32 AOs and MO contraction on the vector units) and BF16 (FP32
+AOs, MO contraction as split-BF16 matrix-core products with FP32
+accumulation); both keep determinants, traces, Jastrow and E_L in FP64.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
 PEAK_HBM = 8.0e12          # bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "co_metropolis_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_09743_amd", "csrc", f)
-                  for f in ("qmc_kernels.hip", "qmc_device.h")]
+                  for f in ("qmc_kernels.hip", "qmc_walker.h", "qmc_device.h", "qmc_api.hip")]
 
 
 def flops_per_walker_step(sysd) -> dict:
@@ -153,11 +155,11 @@ def serving_bench(n_requests: int, steps: int, seed: int = 2506) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=500, help="timed Metropolis steps (one block)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--chunk", type=int, default=10, help="Metropolis steps per launch")
     ap.add_argument("--walkers", type=int, default=65536)
-    ap.add_argument("--burnin", type=int, default=200)
+    ap.add_argument("--burnin", type=int, default=500, help="FP64 equilibration steps")
     ap.add_argument("--system", default="CO")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -210,7 +212,7 @@ def main():
     lp_eq, sg_eq, el_eq = lp.clone(), sg.clone(), el.clone()
 
     results = {}
-    for form in (["fp64"] if args.no_mixed else ["fp64", "fp32"]):
+    for form in (["fp64"] if args.no_mixed else ["fp64", "fp32", "bf16"]):
         st = [X_eq.clone(), lp_eq.clone(), sg_eq.clone(), el_eq.clone()]
         if form != "fp64":  # the mixed chain carries its own log|Psi| and E_L
             st[1], st[2], st[3] = system.eval(st[0], precision=form)

@@ -318,6 +318,62 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
             }
         }
     }
+    // flattened records (see DevSystem): the walker's LW lanes get entries by
+    // greedy longest-first packing so every lane runs the same trip count
+    int G = 1;
+    while (G < std::max(nu, nd)) G <<= 1;
+    const int LW = 2 * G;
+    auto exc_code = [](const Excitation &e) {
+        return (uint32_t)e.rank | ((uint32_t)e.h[0] << 2) | ((uint32_t)e.h[1] << 5) |
+               ((uint32_t)e.p[0] << 8) | ((uint32_t)e.p[1] << 13);
+    };
+    auto ci_words = [](double c, uint32_t *lo, uint32_t *hi) {
+        uint64_t u;
+        memcpy(&u, &c, 8);
+        *lo = (uint32_t)u;
+        *hi = (uint32_t)(u >> 32);
+    };
+    const int det_rows = (n_det + LW - 1) / LW;
+    std::vector<uint4> det_recs((size_t)det_rows * LW, make_uint4(0, 0, 0, 0));
+    for (int n = 0; n < n_det; ++n) {
+        uint4 r;
+        ci_words(ci[n], &r.x, &r.y);
+        r.z = exc_code(ex_up[n]);
+        r.w = exc_code(ex_dn[n]);
+        det_recs[(size_t)(n / LW) * LW + n % LW] = r;
+    }
+    std::vector<std::vector<uint4>> lane_lists(LW);
+    {
+        std::vector<std::pair<std::tuple<int, int, int>, const std::vector<int4> *>> order;
+        for (auto &kv : ent) order.push_back({kv.first, &kv.second});
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto &a, const auto &b) { return a.second->size() > b.second->size(); });
+        for (auto &o : order) {
+            int best = 0;
+            for (int l = 1; l < LW; ++l)
+                if (lane_lists[l].size() < lane_lists[best].size()) best = l;
+            const int spin = std::get<0>(o.first), k = std::get<1>(o.first), v = std::get<2>(o.first);
+            const std::vector<int4> &cl = *o.second;
+            for (size_t q = 0; q < cl.size(); ++q) {
+                const int4 cb = cl[q];
+                const Excitation &other = spin == 0 ? ex_dn[cb.x] : ex_up[cb.x];
+                uint32_t cof = 0;
+                if (cb.y != 0) cof = (cb.y > 0 ? 1u : 2u) | ((uint32_t)cb.z << 2) | ((uint32_t)cb.w << 5);
+                uint4 r;
+                ci_words(ci[cb.x], &r.x, &r.y);
+                r.z = exc_code(other) | (cof << 18);
+                r.w = (q + 1 == cl.size() ? 1u : 0u) | ((uint32_t)spin << 1) | ((uint32_t)k << 2) |
+                      ((uint32_t)v << 5);
+                lane_lists[best].push_back(r);
+            }
+        }
+    }
+    size_t cof_rows = 0;
+    for (auto &l : lane_lists) cof_rows = std::max(cof_rows, l.size());
+    std::vector<uint4> cof_recs(cof_rows * LW, make_uint4(0, 0, 0, 0));
+    for (int l = 0; l < LW; ++l)
+        for (size_t i = 0; i < lane_lists[l].size(); ++i) cof_recs[i * LW + l] = lane_lists[l][i];
+
     std::vector<int4> entries, contribs;
     for (auto &kv : ent) {
         entries.push_back(make_int4(std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
@@ -381,6 +437,8 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     const size_t o_angf = push_bytes(blob, angf.data(), angf.size());
     const std::vector<uint4> frag = mfma_fragments(mo, n_ao, d->n_mo, nmo_pad);
     const size_t o_frag = push_bytes(blob, frag.data(), frag.size());
+    const size_t o_drec = push_bytes(blob, det_recs.data(), det_recs.size());
+    const size_t o_crec = push_bytes(blob, cof_recs.data(), cof_recs.size());
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return QMC_EDEVICE;
@@ -409,8 +467,6 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.n_mo = d->n_mo;
     S.n_det = n_det;
     S.n_entries = n_entries;
-    int G = 1;
-    while (G < std::max(nu, nd)) G <<= 1;
     S.G = G;
     S.LW = 2 * G;
     S.WPW = qmc::kWave / S.LW;
@@ -434,6 +490,10 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.mo_perm = (const int *)(base + o_perm);
     S.ao_angf = (const double *)(base + o_angf);
     S.mfma_tab = (const uint4 *)(base + o_frag);
+    S.det_rows = det_rows;
+    S.cof_rows = (int)cof_rows;
+    S.det_recs = (const uint4 *)(base + o_drec);
+    S.cof_recs = (const uint4 *)(base + o_crec);
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();

@@ -40,6 +40,15 @@ struct DevSystem {
     // BF16 MFMA operand fragments [2 matrices: C^T, C][2 tiles][hi, lo][64 lanes],
     // 8 bf16 each: lane l of tile t holds M[16 t + l % 16][8 (l / 16) + e].
     const uint4 *mfma_tab;
+    // Flattened determinant and cofactor work for the walker's LW lanes.
+    // det_recs [det_rows][LW]: (CI weight as two words, up code, down code);
+    // cof_recs [cof_rows][LW]: (CI weight, code word, target word).  An
+    // excitation code packs rank | h1 << 2 | h2 << 5 | p1 << 8 | p2 << 13; the
+    // code word adds the cofactor (0 unit, 1 +T, 2 -T) | h' << 2 | p' << 5
+    // shifted by 18; the target word is flush | spin << 1 | k << 2 | v << 5.
+    int det_rows, cof_rows;
+    const uint4 *det_recs;
+    const uint4 *cof_recs;
 };
 
 }  // namespace qmc

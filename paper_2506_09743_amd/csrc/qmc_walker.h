@@ -105,6 +105,18 @@ __device__ __forceinline__ double ratio(const double *T, const int *d) {
     return a * T[d[2] * NMO + d[4]] - T[d[1] * NMO + d[4]] * T[d[2] * NMO + d[3]];
 }
 
+// Determinant ratio from a packed excitation code (rank | h1 << 2 |
+// h2 << 5 | p1 << 8 | p2 << 13).
+template <int NMO>
+__device__ __forceinline__ double ratio_code(const double *T, uint32_t c) {
+    const uint32_t k = c & 3u;
+    if (k == 0) return 1.0;
+    const int h1 = (c >> 2) & 7, h2 = (c >> 5) & 7, p1 = (c >> 8) & 31, p2 = (c >> 13) & 31;
+    const double a = T[h1 * NMO + p1];
+    if (k == 1) return a;
+    return a * T[h2 * NMO + p2] - T[h1 * NMO + p2] * T[h2 * NMO + p1];
+}
+
 template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
 template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp(x); }
 template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
@@ -603,30 +615,29 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     // ---- S = sum_n d_n det T_up[H,P] det T_dn[H,P] ----------------------
     const double *Tup = sT, *Tdn = sT + tstride;
     double Sp = 0.0;
-    if (L.wvalid) {
-        for (int n = L.lw; n < S.n_det; n += S.LW) {
-            const int *d = S.dets + n * kDetInts;
-            Sp += S.ci[n] * ratio<NMO>(Tup, d) * ratio<NMO>(Tdn, d + 5);
-        }
+    for (int i = 0; i < S.det_rows; ++i) {
+        const uint4 r = S.det_recs[i * S.LW + L.lw];
+        Sp += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(Tup, r.z) * ratio_code<NMO>(Tdn, r.w);
     }
     const double Ssum = walker_sum(Sp, S.LW);
 
     // ---- cofactor tables C_sigma[k][v] = dS / dT_sigma[k][v] ---------------
-    if (L.wvalid) {
-        for (int t = L.lw; t < S.n_entries; t += S.LW) {
-            const int4 en = S.entries[t];
-            const int end = S.entries[t + 1].w;
-            const double *Ts = en.x == 0 ? Tup : Tdn;
-            const double *To = en.x == 0 ? Tdn : Tup;
-            const int oth = en.x == 0 ? 5 : 0;
-            double val = 0.0;
-            for (int c = en.w; c < end; ++c) {
-                const int4 cb = S.contribs[c];
-                const int *d = S.dets + cb.x * kDetInts;
-                const double cof = cb.y == 0 ? 1.0 : double(cb.y) * Ts[cb.z * NMO + cb.w];
-                val += S.ci[cb.x] * ratio<NMO>(To, d + oth) * cof;
+    // each lane runs its own list of contributions (same length on every
+    // lane) and writes an entry after its last contribution
+    {
+        double acc = 0.0;
+        for (int i = 0; i < S.cof_rows; ++i) {
+            const uint4 r = S.cof_recs[i * S.LW + L.lw];
+            const int spin = (r.w >> 1) & 1;
+            const double *Ts = spin ? Tdn : Tup, *To = spin ? Tup : Tdn;
+            const uint32_t cc = r.z >> 18;
+            const double tv = Ts[((cc >> 2) & 7) * NMO + (cc >> 5)];
+            const double cof = (cc & 3) == 0 ? 1.0 : ((cc & 3) == 1 ? tv : -tv);
+            acc += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(To, r.z & 0x3FFFFu) * cof;
+            if (r.w & 1u) {
+                sC[spin * tstride + ((r.w >> 2) & 7) * NMO + (r.w >> 5)] = acc;
+                acc = 0.0;
             }
-            sC[en.x * tstride + en.y * NMO + en.z] = val;
         }
     }
     __syncthreads();
