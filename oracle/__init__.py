@@ -44,6 +44,7 @@ class _System(C.Structure):
         ("shell_nprim", _ip), ("prim_exp", _dp), ("prim_coef", _dp), ("normalize", C.c_int),
         ("n_mo", C.c_int), ("mo_coef", _dp), ("n_det", C.c_int), ("occ_up", _ip), ("occ_dn", _ip),
         ("ci", _dp), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
+        ("en", _dp), ("een_n", C.c_int), ("een", _dp),
     ]
 
 
@@ -125,6 +126,12 @@ class OracleSystem:
         s.a_par = float(sysd.get("jas_a_par", 0.25))
         s.a_anti = float(sysd.get("jas_a_anti", 0.5))
         s.b = float(sysd.get("jas_b", 1.0))
+        if sysd.get("jas_en") is not None:
+            s.en = f64("jas_en")
+        een = sysd.get("jas_een")
+        if een is not None and len(een) > 0:
+            s.een_n = int(np.asarray(een).shape[0])
+            s.een = f64("jas_een")
         self._keep = keep
         self.s = s
         self.ref = C.byref(s)

@@ -22,7 +22,11 @@
  *     and down determinants depend on disjoint electrons.
  *   - Pade e-e Jastrow K = a r / (1 + b r), a = 1/4 parallel, 1/2
  *     antiparallel (Appendix on additional ansatze, eq. pade_kernel), summed
- *     over pairs i<j (eq. jastrow, e-e term only).
+ *     over pairs i<j (eq. jastrow, e-e term); optionally the many-body
+ *     terms of eq. jastrow with the kernels of the appendix's many-body
+ *     Jastrow subsection: the e-n kernel (w0 r + w1 r^2) / (1 + w2 r) per
+ *     nucleus and the e-e-n kernel sum_mu c_mu f1 f2 f3 over nuclei and
+ *     ordered pairs i > j.
  *   - Kinetic split lap Psi / Psi = lap J + |grad J|^2 + 2 grad J . grad
  *     Sigma / Sigma + lap Sigma / Sigma (Appendix on local energies, with the
  *     Jastrow factor written as exp(J)).
@@ -317,6 +321,80 @@ void or_eval_one(const or_system *s, const double *x, or_detail *out, double *gr
             ven -= s->Z[a] / sqrt(dx * dx + dy * dy + dz * dz);
         }
     }
+    /* Electron-nucleus kernel (appendix on the many-body Jastrow factor,
+       Bertini form): K(r) = (w0 r + w1 r^2) / (1 + w2 r) for every
+       electron-nucleus pair, so with N = w0 r + w1 r^2 and D = 1 + w2 r,
+       K' = N'/D - N w2/D^2 and K'' = N''/D - 2 N' w2/D^2 + 2 N w2^2/D^3. */
+    if (s->en) {
+        for (int i = 0; i < ne; ++i) {
+            for (int a = 0; a < s->n_atoms; ++a) {
+                const double d[3] = {x[3 * i] - s->R[3 * a], x[3 * i + 1] - s->R[3 * a + 1],
+                                     x[3 * i + 2] - s->R[3 * a + 2]};
+                const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                const double w0 = s->en[3 * a], w1 = s->en[3 * a + 1], w2 = s->en[3 * a + 2];
+                const double N = w0 * r + w1 * r * r, N1 = w0 + 2.0 * w1 * r, N2 = 2.0 * w1;
+                const double D = 1.0 + w2 * r;
+                const double K = N / D;
+                const double K1 = N1 / D - N * w2 / (D * D);
+                const double K2 = N2 / D - 2.0 * N1 * w2 / (D * D) + 2.0 * N * w2 * w2 / (D * D * D);
+                J += K;
+                for (int c = 0; c < 3; ++c) gJ[3 * i + c] += K1 * d[c] / r;
+                lapJ += K2 + 2.0 * K1 / r;
+            }
+        }
+    }
+
+    /* Electron-electron-nucleus kernel (same appendix): for every nucleus and
+       every ordered pair i > j, sum_mu c f(a1,b1; r_ai) f(a2,b2; r_aj)
+       f(a3,b3; r_ij) with f(a,b; r) = a r / (1 + b r), f' = a / (1 + b r)^2,
+       f'' = -2 a b / (1 + b r)^3.  Gradient and Laplacian by the product
+       rule, with grad_i r_ai = u_i (unit vector from the nucleus),
+       grad_j r_aj = v_j, grad_i r_ij = -grad_j r_ij = w (unit vector from j
+       to i). */
+    for (int a = 0; a < s->n_atoms && s->een_n > 0; ++a) {
+        for (int i = 0; i < ne; ++i) {
+            for (int j = 0; j < i; ++j) {
+                double u[3], v[3], w[3];
+                for (int c = 0; c < 3; ++c) {
+                    u[c] = x[3 * i + c] - s->R[3 * a + c];
+                    v[c] = x[3 * j + c] - s->R[3 * a + c];
+                    w[c] = x[3 * i + c] - x[3 * j + c];
+                }
+                const double ru = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                const double rv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                const double rw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+                for (int c = 0; c < 3; ++c) { u[c] /= ru; v[c] /= rv; w[c] /= rw; }
+                const double uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+                const double vw = v[0] * w[0] + v[1] * w[1] + v[2] * w[2];
+                for (int m = 0; m < s->een_n; ++m) {
+                    const double *q = s->een + 7 * m;
+                    const double c = q[0];
+                    double f1, d1, e1, f2, d2, e2, f3, d3, e3;
+                    {
+                        const double D = 1.0 + q[2] * ru;
+                        f1 = q[1] * ru / D; d1 = q[1] / (D * D); e1 = -2.0 * q[1] * q[2] / (D * D * D);
+                    }
+                    {
+                        const double D = 1.0 + q[4] * rv;
+                        f2 = q[3] * rv / D; d2 = q[3] / (D * D); e2 = -2.0 * q[3] * q[4] / (D * D * D);
+                    }
+                    {
+                        const double D = 1.0 + q[6] * rw;
+                        f3 = q[5] * rw / D; d3 = q[5] / (D * D); e3 = -2.0 * q[5] * q[6] / (D * D * D);
+                    }
+                    J += c * f1 * f2 * f3;
+                    for (int k = 0; k < 3; ++k) {
+                        gJ[3 * i + k] += c * (d1 * u[k] * f2 * f3 + f1 * f2 * d3 * w[k]);
+                        gJ[3 * j + k] += c * (f1 * d2 * v[k] * f3 - f1 * f2 * d3 * w[k]);
+                    }
+                    const double lap3 = e3 + 2.0 * d3 / rw;
+                    lapJ += c * f2 * ((e1 + 2.0 * d1 / ru) * f3 + 2.0 * d1 * d3 * uw + f1 * lap3);
+                    lapJ += c * f1 * ((e2 + 2.0 * d2 / rv) * f3 - 2.0 * d2 * d3 * vw + f2 * lap3);
+                }
+            }
+        }
+    }
+
     double kin = lapJ + lapS;
     for (int q = 0; q < 3 * ne; ++q) kin += gJ[q] * gJ[q] + 2.0 * gJ[q] * gS[q];
     const double e_kin = -0.5 * kin;

@@ -35,6 +35,10 @@ typedef struct {
     const int *occ_dn;        /* [n_det][n_dn] */
     const double *ci;         /* [n_det] */
     double a_par, a_anti, b;  /* Pade e-e Jastrow */
+    const double *en;         /* [n_atoms][3] e-n kernel (omega0, omega1, omega2)
+                                 per nucleus; NULL: no e-n term */
+    int een_n;                /* terms of the e-e-n kernel; 0: none */
+    const double *een;        /* [een_n][7]: c, a1, b1, a2, b2, a3, b3 */
 } or_system;
 
 /* Per-walker detail of one evaluation. */

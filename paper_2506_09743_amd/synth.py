@@ -248,6 +248,36 @@ def make_system(name: str, bond_scale: float = 1.0, seed: int | None = None) -> 
     return MAKERS[name](bond_scale=bond_scale, seed=seed)
 
 
+MBJ_SEED = {"H2": 2000, "LiH": 2001, "CO": 2002, "Li2": 2003}
+
+
+def with_many_body_jastrow(sysd: dict, seed: int, n_terms: int = 5, symmetric: bool = True) -> dict:
+    """A copy of ``sysd`` with the many-body Jastrow terms drawn:
+    ``jas_en`` [n_atoms, 3] = (omega0, omega1, omega2) per nucleus with
+    omega0 ~ U[-0.2, 0.2], omega1 ~ U[-0.05, 0] (no growth at large r),
+    omega2 ~ U[0.5, 2]; ``jas_een`` [n_terms, 7] = (c, a1, b1, a2, b2, a3, b3)
+    with c ~ N(0, 0.05^2), a ~ U[0.2, 1], b ~ U[0.5, 2].  ``symmetric``
+    draws a2 = a1 and b2 = b1, so exp(J) is symmetric under the exchange of
+    any two electrons."""
+    rng = np.random.default_rng(seed)
+    d = dict(sysd)
+    na = len(sysd["Z"])
+    en = np.empty((na, 3))
+    en[:, 0] = rng.uniform(-0.2, 0.2, na)
+    en[:, 1] = rng.uniform(-0.05, 0.0, na)
+    en[:, 2] = rng.uniform(0.5, 2.0, na)
+    een = np.empty((n_terms, 7))
+    een[:, 0] = rng.normal(0.0, 0.05, n_terms)
+    for k in (1, 3, 5):
+        een[:, k] = rng.uniform(0.2, 1.0, n_terms)
+        een[:, k + 1] = rng.uniform(0.5, 2.0, n_terms)
+    if symmetric:
+        een[:, 3], een[:, 4] = een[:, 1], een[:, 2]
+    d["jas_en"] = en
+    d["jas_een"] = een
+    return d
+
+
 def electron_atoms(sysd: dict) -> list:
     """Home atom of each electron: atoms filled by nuclear charge in atom
     order, spins alternating up/down; returns the atom index per electron in
