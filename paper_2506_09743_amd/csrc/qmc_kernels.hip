@@ -17,7 +17,7 @@ struct WalkerResult {
 // lane of the block must call it (it contains block barriers); results are
 // identical on all lanes of a walker.
 template <int NMO, typename RT, int MF>
-__device__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
+__device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
                                     double x1, double x2, void *stage) {
     Core<NMO> c;
     core_stages<NMO, RT, MF>(S, L, wsm, x0, x1, x2, c, stage);

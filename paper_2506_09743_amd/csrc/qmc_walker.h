@@ -117,8 +117,43 @@ __device__ __forceinline__ double ratio_code(const double *T, uint32_t c) {
     return a * T[h2 * NMO + p2] - T[h1 * NMO + p2] * T[h2 * NMO + p1];
 }
 
+// d = a * b + c as one three-address FMA: the constant c stays in the
+// register that holds it for the whole kernel instead of being copied into
+// the accumulator of a two-address FMA before every use.
+__device__ __forceinline__ double fma_c(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// exp(x) in FP64: Cody-Waite reduction x = n ln2 + r, |r| <= ln2 / 2 (ln2
+// split into a head with trailing zero bits, so n * head is exact, and a
+// tail), the degree-13 Taylor polynomial of e^r (truncation below 5e-18
+// relative), and a scale by 2^n that rounds once, so underflow to
+// subnormals and zero needs no separate branch.  Within 1 ulp of the exact
+// value over the arguments the orbitals use (x <= 0).
+__device__ __forceinline__ double exp_f64(double x) {
+    const double n = __builtin_rint(x * 1.4426950408889634);
+    double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
+    r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
+    double p = fma_c(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);
+    p = fma_c(p, r, 1.0 / 39916800.0);
+    p = fma_c(p, r, 1.0 / 3628800.0);
+    p = fma_c(p, r, 1.0 / 362880.0);
+    p = fma_c(p, r, 1.0 / 40320.0);
+    p = fma_c(p, r, 1.0 / 5040.0);
+    p = fma_c(p, r, 1.0 / 720.0);
+    p = fma_c(p, r, 1.0 / 120.0);
+    p = fma_c(p, r, 1.0 / 24.0);
+    p = fma_c(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)n);
+}
+
 template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
-template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp_f64(x); }
 template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
 
 template <typename RT> __device__ __forceinline__ const RT *mo_table(const DevSystem &S);
@@ -177,13 +212,20 @@ __device__ __forceinline__ void mo_values(const DevSystem &S, double x0, double 
     const RT *C = mo_table<RT>(S);
     int p = 0;
     const RT *crow = C;
+    int atom = -1;
+    RT dx = RT(0), dy = RT(0), dz = RT(0), r2 = RT(0), r = RT(0);
     for (int sh = 0; sh < S.n_shells; ++sh) {
         const int4 si = S.shells[sh];
-        const double *A = S.atoms + 4 * si.x;
-        // displacement in FP64, cast afterwards
-        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
-        const RT r2 = dx * dx + dy * dy + dz * dz;
-        const RT r = sqrt(r2);
+        if (si.x != atom) {  // shells of one atom share the geometry
+            atom = si.x;
+            const double *A = S.atoms + 4 * atom;
+            // displacement in FP64, cast afterwards
+            dx = RT(x0 - A[0]);
+            dy = RT(x1 - A[1]);
+            dz = RT(x2 - A[2]);
+            r2 = dx * dx + dy * dy + dz * dz;
+            r = sqrt(r2);
+        }
         RT Rv, Rd, Rl;
         shell_radial<RT, false>(S, p, si.w, si.y, si.z, r, r2, RT(0), Rv, Rd, Rl);
         p += si.w;
@@ -220,13 +262,20 @@ __device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, doub
     int p = 0;
     const RT *crow = C;
     double G0 = 0.0, G1 = 0.0, G2 = 0.0, L = 0.0;
+    int atom = -1;
+    RT dx = RT(0), dy = RT(0), dz = RT(0), r2 = RT(0), r = RT(0), rinv = RT(0);
     for (int sh = 0; sh < S.n_shells; ++sh) {
         const int4 si = S.shells[sh];
-        const double *A = S.atoms + 4 * si.x;
-        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
-        const RT r2 = dx * dx + dy * dy + dz * dz;
-        const RT r = sqrt(r2);
-        const RT rinv = RT(1) / r;
+        if (si.x != atom) {  // shells of one atom share the geometry
+            atom = si.x;
+            const double *A = S.atoms + 4 * atom;
+            dx = RT(x0 - A[0]);
+            dy = RT(x1 - A[1]);
+            dz = RT(x2 - A[2]);
+            r2 = dx * dx + dy * dy + dz * dz;
+            r = sqrt(r2);
+            rinv = RT(1) / r;
+        }
         RT Rv, Rd, Rl;
         shell_radial<RT, true>(S, p, si.w, si.y, si.z, r, r2, rinv, Rv, Rd, Rl);
         p += si.w;
@@ -345,12 +394,19 @@ __device__ __forceinline__ void mo_values_mfma(const DevSystem &S, int lane, voi
                                                double x1, double x2, float (&phi)[NMO]) {
     const Stage st = make_stage(stage_base);
     int p = 0, mu = 0;
+    int atom = -1;
+    float dx = 0.f, dy = 0.f, dz = 0.f, r2 = 0.f, r = 0.f;
     for (int sh = 0; sh < S.n_shells; ++sh) {
         const int4 si = S.shells[sh];
-        const double *A = S.atoms + 4 * si.x;
-        const float dx = float(x0 - A[0]), dy = float(x1 - A[1]), dz = float(x2 - A[2]);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float r = sqrtf(r2);
+        if (si.x != atom) {  // shells of one atom share the geometry
+            atom = si.x;
+            const double *A = S.atoms + 4 * atom;
+            dx = float(x0 - A[0]);
+            dy = float(x1 - A[1]);
+            dz = float(x2 - A[2]);
+            r2 = dx * dx + dy * dy + dz * dz;
+            r = sqrtf(r2);
+        }
         float Rv, Rd, Rl;
         shell_radial<float, false>(S, p, si.w, si.y, si.z, r, r2, 0.f, Rv, Rd, Rl);
         p += si.w;
@@ -397,13 +453,20 @@ __device__ __forceinline__ void sigma_derivs_t(const DevSystem &S, double x0, do
                                                double &lap) {
     int p = 0, mu = 0;
     double G0 = 0.0, G1 = 0.0, G2 = 0.0, Lp = 0.0;
+    int atom = -1;
+    RT dx = RT(0), dy = RT(0), dz = RT(0), r2 = RT(0), r = RT(0), rinv = RT(0);
     for (int sh = 0; sh < S.n_shells; ++sh) {
         const int4 si = S.shells[sh];
-        const double *A = S.atoms + 4 * si.x;
-        const RT dx = RT(x0 - A[0]), dy = RT(x1 - A[1]), dz = RT(x2 - A[2]);
-        const RT r2 = dx * dx + dy * dy + dz * dz;
-        const RT r = sqrt(r2);
-        const RT rinv = RT(1) / r;
+        if (si.x != atom) {  // shells of one atom share the geometry
+            atom = si.x;
+            const double *A = S.atoms + 4 * atom;
+            dx = RT(x0 - A[0]);
+            dy = RT(x1 - A[1]);
+            dz = RT(x2 - A[2]);
+            r2 = dx * dx + dy * dy + dz * dz;
+            r = sqrt(r2);
+            rinv = RT(1) / r;
+        }
         RT Rv, Rd, Rl;
         shell_radial<RT, true>(S, p, si.w, si.y, si.z, r, r2, rinv, Rv, Rd, Rl);
         p += si.w;
