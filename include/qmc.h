@@ -91,6 +91,15 @@ typedef struct {
     double jas_a_par;           /* Pade numerator for parallel spins (1/4) */
     double jas_a_anti;          /* Pade numerator for antiparallel spins (1/2) */
     double jas_b;               /* Pade denominator parameter (omega), >= 0 */
+    /* Many-body terms of eq. jastrow (appendix, many-body Jastrow factor).
+       e-n kernel per nucleus: K(r) = (w0 r + w1 r^2) / (1 + w2 r);
+       e-e-n kernel: sum over nuclei a and electron pairs i > j (electron
+       order as above) of sum_mu c_mu f(a1,b1; r_ai) f(a2,b2; r_aj)
+       f(a3,b3; r_ij), f(a,b; r) = a r / (1 + b r).  Denominators must stay
+       positive for r >= 0: w2 >= 0 and every b >= 0. */
+    const double *jas_en;       /* [n_atoms][3] (w0, w1, w2), or NULL: no e-n term */
+    int32_t jas_een_n;          /* e-e-n terms, 0..8 (0: none) */
+    const double *jas_een;      /* [jas_een_n][7] (c, a1, b1, a2, b2, a3, b3) */
 } qmc_system_desc;
 
 typedef struct qmc_system qmc_system;
@@ -141,7 +150,8 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
      d_deloc_dR     [W][n_atoms][3]  d E_L / d R_alpha (includes V_nn)
    Any output may be NULL; at least one must not be.  d_X as in
    qmc_eval_psi_eloc.  Returns QMC_EUNSUPPORTED when the walker tables do not
-   fit the 160 KiB of LDS of a compute unit. */
+   fit the 160 KiB of LDS of a compute unit, and for systems with many-body
+   Jastrow terms (their parameters have no slot in theta). */
 qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
                     double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream);
 

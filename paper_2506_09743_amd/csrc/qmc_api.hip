@@ -174,6 +174,18 @@ qmc_status validate(const qmc_system_desc *d) {
     }
     if (!is_finite(d->jas_a_par) || !is_finite(d->jas_a_anti) || !is_finite(d->jas_b) || d->jas_b < 0.0)
         return QMC_EINVAL;
+    if (d->jas_en)
+        for (int a = 0; a < d->n_atoms; ++a) {
+            const double *w = d->jas_en + 3 * a;
+            if (!is_finite(w[0]) || !is_finite(w[1]) || !is_finite(w[2]) || w[2] < 0.0) return QMC_EINVAL;
+        }
+    if (d->jas_een_n < 0 || d->jas_een_n > qmc::kMaxEen) return QMC_EINVAL;
+    if (d->jas_een_n > 0 && !d->jas_een) return QMC_EINVAL;
+    for (int m = 0; m < d->jas_een_n; ++m)
+        for (int k = 0; k < 7; ++k) {
+            const double v = d->jas_een[7 * m + k];
+            if (!is_finite(v) || ((k == 2 || k == 4 || k == 6) && v < 0.0)) return QMC_EINVAL;
+        }
     return QMC_OK;
 }
 
@@ -439,6 +451,8 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     const size_t o_frag = push_bytes(blob, frag.data(), frag.size());
     const size_t o_drec = push_bytes(blob, det_recs.data(), det_recs.size());
     const size_t o_crec = push_bytes(blob, cof_recs.data(), cof_recs.size());
+    const size_t o_jen = push_bytes(blob, d->jas_en, d->jas_en ? (size_t)3 * d->n_atoms : 0);
+    const size_t o_jeen = push_bytes(blob, d->jas_een, (size_t)7 * d->jas_een_n);
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return QMC_EDEVICE;
@@ -494,6 +508,9 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.cof_rows = (int)cof_rows;
     S.det_recs = (const uint4 *)(base + o_drec);
     S.cof_recs = (const uint4 *)(base + o_crec);
+    S.jas_en = d->jas_en ? (const double *)(base + o_jen) : nullptr;
+    S.jas_een = (const double *)(base + o_jeen);
+    S.een_n = d->jas_een_n;
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
@@ -558,6 +575,7 @@ qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlo
     if (W == 0) return QMC_OK;
     if (!d_X || (!d_dlogpsi && !d_deloc_dtheta && !d_dlogpsi_dR && !d_deloc_dR)) return QMC_EINVAL;
     if (qmc::grad_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
+    if (sys->S.jas_en || sys->S.een_n > 0) return QMC_EUNSUPPORTED;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
     hipError_t e = qmc::launch_grad(sys->S, d_X, W, d_dlogpsi, d_deloc_dtheta, d_dlogpsi_dR, d_deloc_dR,

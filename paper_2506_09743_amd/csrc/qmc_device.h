@@ -49,6 +49,14 @@ struct DevSystem {
     int det_rows, cof_rows;
     const uint4 *det_recs;
     const uint4 *cof_recs;
+    // Many-body Jastrow: e-n kernel (w0, w1, w2) per nucleus (nullptr: none)
+    // and e-e-n terms (c, a1, b1, a2, b2, a3, b3) x een_n.
+    const double *jas_en;
+    const double *jas_een;
+    int een_n;
 };
+
+// Largest number of e-e-n terms.
+constexpr int kMaxEen = 8;
 
 }  // namespace qmc

@@ -152,6 +152,17 @@ __device__ __forceinline__ double exp_f64(double x) {
     return __builtin_amdgcn_ldexp(p, (int)n);
 }
 
+// 1 / x for x >= 1 (the Pade-type denominators 1 + b r): the hardware
+// reciprocal estimate refined by two Newton steps, within an ulp or so of
+// the quotient.
+__device__ __forceinline__ double rcp_ge1(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
 template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
 template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp_f64(x); }
 template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
@@ -506,15 +517,28 @@ __device__ __forceinline__ void sigma_derivs_t(const DevSystem &S, double x0, do
     lap = Lp;
 }
 
-// LDS of one walker: T tables [2][nmax][NMO] (nmax = max(n_up, n_dn)),
-// then a region shared by the positions + pivot rows (before the
-// determinant stage) and the cofactor tables [2][nmax][NMO] (after it).
+// LDS of one walker (doubles): T tables [2][nmax][NMO] at 0 (nmax =
+// max(n_up, n_dn)) and the cofactor tables [2][nmax][NMO] after them, both
+// written from the determinant stage on.  Before it the same space holds
+// the e-e-n factor table (een_table doubles at 0, when e-e-n terms exist)
+// and the positions [LW][3] + pivot rows [2][NMO] at pos_offset.
+__host__ __device__ inline int een_table(const DevSystem &S) {
+    return S.een_n > 0 ? S.LW * S.n_atoms * (2 * S.een_n + 4) : 0;
+}
+
+template <int NMO>
+__host__ __device__ inline int pos_offset(const DevSystem &S) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int t = 2 * nmax * NMO, f = een_table(S);
+    return f > t ? f : t;
+}
+
 template <int NMO>
 __host__ __device__ inline int walker_lds(const DevSystem &S) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
-    const int t = 2 * nmax * NMO;
-    const int a = 3 * S.LW + 2 * NMO;
-    return t + (a > t ? a : t);
+    const int tc = 4 * nmax * NMO;
+    const int pp = pos_offset<NMO>(S) + 3 * S.LW + 2 * NMO;
+    return tc > pp ? tc : pp;
 }
 
 // Per-lane results of the stages every evaluation shares.
@@ -538,10 +562,14 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
     const int tstride = nmax * NMO;          // doubles per spin table
     double *sT = wsm;                        // [2][nmax][NMO]
-    double *sX = sT + 2 * tstride;           // shared region
-    double *sC = sX;                         // [2][nmax][NMO] after the elimination
-    double *sPos = sX;                       // [LW][3] before it
-    double *sPiv = sX + 3 * S.LW;            // [2][NMO] during it
+    double *sC = sT + 2 * tstride;           // [2][nmax][NMO] after the elimination
+    double *sPos = wsm + pos_offset<NMO>(S); // [LW][3] before it
+    double *sPiv = sPos + 3 * S.LW;          // [2][NMO] during it
+    // e-e-n table before the elimination: per lane [n_atoms][een_n][2]
+    // factor values (f1, f2) of its electron, then [n_atoms][4] geometry
+    // (r, unit vector from the nucleus)
+    double *sF = wsm;
+    double *sG = wsm + S.LW * S.n_atoms * 2 * S.een_n;
     double *Tg = sT + L.grp * tstride;
     double *Cg = sC + L.grp * tstride;
     double *piv_row = sPiv + L.grp * NMO;
@@ -554,6 +582,25 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     sPos[3 * L.lw + 0] = x0;
     sPos[3 * L.lw + 1] = x1;
     sPos[3 * L.lw + 2] = x2;
+    if (S.een_n > 0 && L.active) {
+        for (int a = 0; a < S.n_atoms; ++a) {
+            const double *A = S.atoms + 4 * a;
+            const double e0 = x0 - A[0], e1 = x1 - A[1], e2 = x2 - A[2];
+            const double u = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+            const double ui = 1.0 / u;
+            double *g = sG + (L.lw * S.n_atoms + a) * 4;
+            g[0] = u;
+            g[1] = e0 * ui;
+            g[2] = e1 * ui;
+            g[3] = e2 * ui;
+            double *f = sF + (L.lw * S.n_atoms + a) * 2 * S.een_n;
+            for (int m = 0; m < S.een_n; ++m) {
+                const double *q = S.jas_een + 7 * m;
+                f[2 * m] = q[1] * u * rcp_ge1(1.0 + q[2] * u);
+                f[2 * m + 1] = q[3] * u * rcp_ge1(1.0 + q[4] * u);
+            }
+        }
+    }
     __syncthreads();
 
     // ---- Pade e-e Jastrow and Coulomb terms of this electron -------------
@@ -582,7 +629,55 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         for (int a = 0; a < S.n_atoms; ++a) {
             const double *A = S.atoms + 4 * a;
             const double d0 = x0 - A[0], d1 = x1 - A[1], d2 = x2 - A[2];
-            vpot -= A[3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            vpot -= A[3] / r;
+            if (S.jas_en) {
+                // e-n kernel K = N / D, N = w0 r + w1 r^2, D = 1 + w2 r:
+                // K' = (N' - K D') / D and K'' = (N'' - 2 K' D') / D
+                const double *w = S.jas_en + 3 * a;
+                const double q = 1.0 / (1.0 + w[2] * r), rinv = 1.0 / r;
+                const double K = (w[0] + w[1] * r) * r * q;
+                const double K1 = (w[0] + 2.0 * w[1] * r - K * w[2]) * q;
+                const double K2 = (2.0 * w[1] - 2.0 * K1 * w[2]) * q;
+                J += K;
+                gJ0 += K1 * d0 * rinv;
+                gJ1 += K1 * d1 * rinv;
+                gJ2 += K1 * d2 * rinv;
+                lapJ += K2 + 2.0 * K1 * rinv;
+            }
+        }
+        // e-e-n kernel: for the ordered pair (i, j), i > j, the term is
+        // c f1(r_ai) f2(r_aj) f3(r_ij).  This electron takes the role of i
+        // against lower-numbered partners and of j against higher ones; its
+        // own factor carries the derivatives, the partner's factor is a
+        // value from the table.  The pair's value is counted at i.
+        for (int j = 0; j < S.ne && S.een_n > 0; ++j) {
+            if (j == L.e) continue;
+            const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
+            const bool first = L.e > j;
+            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double rinv = 1.0 / r;
+            const double w0 = d0 * rinv, w1 = d1 * rinv, w2 = d2 * rinv;
+            for (int m = 0; m < S.een_n; ++m) {
+                const double *q = S.jas_een + 7 * m;
+                const double q3 = rcp_ge1(1.0 + q[6] * r);
+                const double f3 = q[5] * r * q3, f31 = q[5] * q3 * q3, f32 = -2.0 * q[6] * f31 * q3;
+                const double ao = first ? q[1] : q[3], bo = first ? q[2] : q[4];
+                for (int a = 0; a < S.n_atoms; ++a) {
+                    const double *g = sG + (L.lw * S.n_atoms + a) * 4;
+                    const double u = g[0];
+                    const double qo = rcp_ge1(1.0 + bo * u);
+                    const double fo = ao * u * qo, fo1 = ao * qo * qo, fo2 = -2.0 * bo * fo1 * qo;
+                    const double cp = q[0] * sF[((lj * S.n_atoms + a) * S.een_n + m) * 2 + (first ? 1 : 0)];
+                    const double uw = g[1] * w0 + g[2] * w1 + g[3] * w2;
+                    if (first) J += cp * fo * f3;
+                    gJ0 += cp * (fo1 * f3 * g[1] + fo * f31 * w0);
+                    gJ1 += cp * (fo1 * f3 * g[2] + fo * f31 * w1);
+                    gJ2 += cp * (fo1 * f3 * g[3] + fo * f31 * w2);
+                    lapJ += cp * ((fo2 + 2.0 * fo1 / u) * f3 + 2.0 * fo1 * f31 * uw + fo * (f32 + 2.0 * f31 * rinv));
+                }
+            }
         }
     }
 

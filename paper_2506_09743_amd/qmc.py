@@ -43,7 +43,7 @@ class qmc_system_desc(C.Structure):
         ("shell_nprim", _ip), ("prim_exp", _dp), ("prim_coef", _dp), ("normalize", C.c_int32),
         ("n_mo", C.c_int32), ("mo_coef", _dp), ("n_det", C.c_int32), ("occ_up", _ip),
         ("occ_dn", _ip), ("ci", _dp), ("jas_a_par", C.c_double), ("jas_a_anti", C.c_double),
-        ("jas_b", C.c_double),
+        ("jas_b", C.c_double), ("jas_en", _dp), ("jas_een_n", C.c_int32), ("jas_een", _dp),
     ]
 
 
@@ -126,6 +126,12 @@ def make_desc(sysd: dict):
     d.jas_a_par = float(sysd.get("jas_a_par", 0.25))
     d.jas_a_anti = float(sysd.get("jas_a_anti", 0.5))
     d.jas_b = float(sysd.get("jas_b", 1.0))
+    if sysd.get("jas_en") is not None:
+        d.jas_en = f64("jas_en")
+    een = sysd.get("jas_een")
+    if een is not None and len(een) > 0:
+        d.jas_een_n = int(np.asarray(een).shape[0])
+        d.jas_een = f64("jas_een")
     return d, keep
 
 

@@ -4,6 +4,7 @@ device."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2506_09743_amd import qmc, synth
@@ -88,6 +89,40 @@ def test_valid_create_needs_a_device():
         s = qmc.System(d)
         assert s.param_count == d["prim_exp"].size + d["mo_coef"].size + 1
         s.close()
+    else:
+        with pytest.raises(qmc.QmcError) as ei:
+            qmc.System(d)
+        assert ei.value.status == qmc.QMC_EDEVICE
+
+
+def _mbj_bad(mutate):
+    d = synth.with_many_body_jastrow(synth.make_system("LiH"), 1)
+    d["jas_en"] = d["jas_en"].copy()
+    d["jas_een"] = d["jas_een"].copy()
+    mutate(d)
+    return d
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda d: d["jas_en"].__setitem__((0, 2), -1.0),
+    lambda d: d["jas_en"].__setitem__((1, 0), float("inf")),
+    lambda d: d["jas_een"].__setitem__((0, 4), -0.5),
+    lambda d: d["jas_een"].__setitem__((2, 0), float("nan")),
+    lambda d: d.__setitem__("jas_een", np.ones((9, 7))),
+], ids=["e-n w2 < 0", "e-n infinite", "e-e-n b < 0", "e-e-n NaN", "more than 8 terms"])
+def test_create_rejects_invalid_many_body_terms(mutate):
+    with pytest.raises(qmc.QmcError) as ei:
+        qmc.System(_mbj_bad(mutate))
+    assert ei.value.status == qmc.QMC_EINVAL
+
+
+def test_valid_many_body_terms_pass_validation():
+    """A valid many-body system gets past validation (to the device check
+    when no GPU is present)."""
+    import torch
+    d = synth.with_many_body_jastrow(synth.make_system("CO"), 2)
+    if torch.cuda.is_available():
+        qmc.System(d).close()
     else:
         with pytest.raises(qmc.QmcError) as ei:
             qmc.System(d)

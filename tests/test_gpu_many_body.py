@@ -1,0 +1,141 @@
+"""Many-body Jastrow terms of eq. jastrow (e-n and e-e-n kernels of the
+appendix's many-body Jastrow subsection) on the HIP path against the FP64
+oracle, through the C ABI, to the same bar as the Pade-only parity tests:
+evaluation parity on all four molecules (several waves and a ragged tail),
+CO at its full 65536 walkers on sampled walkers, Metropolis decisions step
+by step, the mixed forms' errors, zero parameters reproducing the Pade-only
+results, and qmc_grad declining many-body systems.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_09743_amd import synth
+from parity_helpers import LOG_TOL, _compare, _one_step_margin
+
+pytestmark = pytest.mark.gpu
+
+
+def _mbj(name, symmetric=True, amplify=False):
+    d = synth.with_many_body_jastrow(synth.make_system(name), synth.MBJ_SEED[name], symmetric=symmetric)
+    if amplify:
+        d["jas_een"] = d["jas_een"].copy()
+        d["jas_een"][:, 0] *= 10.0
+        d["jas_en"] = d["jas_en"] * np.array([3.0, 3.0, 1.0])
+    return d
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.mark.parametrize("name,W,symmetric,amplify", [
+    ("H2", 1000, True, False), ("LiH", 997, False, True), ("Li2", 601, True, False),
+    ("CO", 515, True, False), ("CO", 130, False, True)])
+def test_mbj_eval_parity(torch_cuda, oracle_mod, name, W, symmetric, amplify):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _mbj(name, symmetric, amplify)
+    X = synth.init_walkers(sysd, W, 78)
+    s = qmc.System(sysd)
+    lp, sg, el = s.eval(torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp.cpu().numpy(), sg.cpu().numpy(),
+             el.cpu().numpy(), f"{name} many-body eval")
+    s.close()
+
+
+def test_mbj_full_size_co_sampled(torch_cuda, oracle_mod):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _mbj("CO")
+    X = synth.init_walkers(sysd, 65536, synth.WALKER_SEED["CO"])
+    s = qmc.System(sysd)
+    lp, sg, el = s.eval(torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(2).choice(65536, 256, replace=False))
+    idx[-1] = 65535
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X[idx], lp.cpu().numpy()[idx],
+             sg.cpu().numpy()[idx], el.cpu().numpy()[idx], "CO many-body 64k sampled")
+    s.close()
+
+
+@pytest.mark.parametrize("name,W,steps", [("LiH", 192, 10), ("CO", 64, 6)])
+def test_mbj_metropolis_stepwise_parity(torch_cuda, oracle_mod, name, W, steps):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _mbj(name, symmetric=(name == "CO"), amplify=(name == "LiH"))
+    o = oracle_mod.OracleSystem(sysd)
+    s = qmc.System(sysd)
+    seed, sigma = synth.PHILOX_SEED[name], 0.2
+    X = synth.init_walkers(sysd, W, 6)
+    lp, sg, el = o.eval(X)
+    flips = 0
+    for t in range(steps):
+        Xo, lpo, sgo, elo, _, log = o.metropolis(X, lp, sg, el, 1, sigma, seed, step0=t, want_log=True)
+        tX = torch.from_numpy(X.copy()).cuda()
+        tl, ts, te = (torch.from_numpy(v.copy()).cuda() for v in (lp, sg, el))
+        acc = s.metropolis(tX, tl, ts, te, 1, sigma, seed, step0=t)
+        torch.cuda.synchronize()
+        mism = acc.cpu().numpy()[:, 2] != log[0]
+        if mism.any():
+            margin = _one_step_margin(o, sysd, X, lp, seed, t, sigma, oracle_mod)
+            assert np.all(margin[mism] < 1e-9), f"step {t}: decision mismatch away from a tie"
+            flips += int(mism.sum())
+        same = ~mism
+        assert np.max(np.abs(tX.cpu().numpy()[same] - Xo[same])) < 1e-12
+        glp = tl.cpu().numpy()
+        assert np.max(np.abs(glp[same] - lpo[same]) / np.maximum(1, np.abs(lpo[same]))) < LOG_TOL
+        X, lp, sg, el = Xo, lpo, sgo, elo
+    assert flips == 0
+    s.close()
+
+
+@pytest.mark.parametrize("prec,med_tol", [("fp32", 1e-4), ("bf16", 2e-3)])
+def test_mbj_mixed_error(torch_cuda, oracle_mod, prec, med_tol):
+    """The Jastrow stays FP64 in the mixed forms: their error is the orbital
+    error alone, as without the many-body terms."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _mbj("CO")
+    X = synth.init_walkers(sysd, 256, 9)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
+    rlp, rsg, rel = oracle_mod.OracleSystem(sysd).eval(X)
+    ok = np.isfinite(rel) & np.isfinite(el)
+    err = np.abs(el[ok] - rel[ok])
+    print(f"CO many-body {prec}: median |dE_L| {np.median(err):.2e}")
+    assert np.median(err) < med_tol
+    s.close()
+
+
+def test_mbj_zero_parameters_equal_pade(torch_cuda):
+    """Zero e-n parameters and zero e-e-n weights give the Pade-only results
+    bit for bit (the added terms are exact zeros)."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    base = synth.make_system("Li2")
+    d = synth.with_many_body_jastrow(base, 1)
+    d["jas_en"] = np.zeros_like(d["jas_en"])
+    d["jas_een"] = d["jas_een"].copy()
+    d["jas_een"][:, 0] = 0.0
+    X = torch.from_numpy(synth.init_walkers(base, 200, 3)).cuda()
+    a, b = qmc.System(base), qmc.System(d)
+    for u, v in zip(a.eval(X), b.eval(X)):
+        assert torch.equal(torch.nan_to_num(u, nan=7.0), torch.nan_to_num(v, nan=7.0))
+    a.close()
+    b.close()
+
+
+def test_mbj_grad_declined(torch_cuda):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _mbj("LiH")
+    s = qmc.System(sysd)
+    X = torch.from_numpy(synth.init_walkers(sysd, 8, 1)).cuda()
+    with pytest.raises(qmc.QmcError) as e:
+        s.grad(X)
+    assert e.value.status == qmc.QMC_EUNSUPPORTED
+    s.close()
