@@ -215,6 +215,49 @@ def many_body_bench(sysd, args, dev, seed) -> dict:
             "mean_energy": float(np.nanmean(acc.cpu().numpy()[:, 0]) / args.steps)}
 
 
+def sd_sweep_bench(args, dev) -> list:
+    """Determinant-count sweep on CO, SD(2,2) .. SD(10,10) (4 .. 876
+    determinants): E_L evaluation time of the low-rank method and of the
+    explicit per-configuration method at 1000 and at the full walker count,
+    and the low-rank Metropolis step time at the full walker count."""
+    import torch
+    from paper_2506_09743_amd import qmc, synth
+    base = synth.make_system("CO")
+
+    def timed(fn, reps=3):
+        fn()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    rows = []
+    for n in (2, 4, 6, 8, 10):
+        sysd = synth.with_sd_expansion(base, n, 5)
+        system = qmc.System(sysd, device=0)
+        row = {"sd": f"SD({n},{n})", "dets": len(sysd["ci"])}
+        for W in (1000, args.walkers):
+            X = torch.from_numpy(synth.init_walkers(sysd, W, synth.WALKER_SEED["CO"])).to(dev)
+            outs = [torch.empty(W, dtype=torch.float64, device=dev) for _ in range(3)]
+            t_tab = timed(lambda: qmc.qmc_eval_psi_eloc(system.handle, qmc.QMC_FP64, X, *outs))
+            t_exp = timed(lambda: qmc.qmc_eval_psi_eloc(system.handle, qmc.QMC_FP64_EXPLICIT, X, *outs))
+            row[f"W{W}"] = {"eval_ms_low_rank": t_tab, "eval_ms_explicit": t_exp,
+                            "explicit_over_low_rank": t_exp / t_tab}
+            if W == args.walkers:
+                lp, sg, el = system.eval(X)
+                acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+                t_mc = timed(lambda: system.metropolis(X, lp, sg, el, args.chunk, 0.2, 1, acc=acc))
+                row[f"W{W}"]["metropolis_walker_steps_per_s"] = W * args.chunk / (t_mc * 1e-3)
+        rows.append(row)
+        system.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +271,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-many-body", action="store_true",
                     help="skip the many-body Jastrow (e-n + e-e-n) measurement")
+    ap.add_argument("--no-sd-sweep", action="store_true",
+                    help="skip the determinant-count sweep (low-rank vs explicit)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests in the serving measurement (0: skip)")
@@ -324,6 +369,9 @@ def main():
     many_body = None
     if not args.no_many_body:
         many_body = many_body_bench(sysd, args, dev, seed)
+    sd_sweep = None
+    if not args.no_sd_sweep and args.system == "CO":
+        sd_sweep = sd_sweep_bench(args, dev)
 
     fl = flops_per_walker_step(sysd)
     main_form = results["fp64"]
@@ -369,6 +417,7 @@ def main():
         "forms": results,
         "serving": serving,
         "many_body_jastrow": many_body,
+        "determinant_sweep": sd_sweep,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -56,12 +56,21 @@ typedef enum {
                         each operand split into high and low BF16 parts
                         (hi*hi + hi*lo + lo*hi, about 16 significant bits);
      QMC_MIXED_BF16_X1  one BF16 product per pair (8 significant bits).
-   The BF16 forms need n_ao <= 32. */
+   The BF16 forms need n_ao <= 32.
+   QMC_FP64_EXPLICIT is FP64 with a different determinant method, kept for
+   comparison: every distinct spin configuration of the CI expansion is
+   factorised on its own (the explicit evaluation that the low-rank
+   excited-determinant scheme of eq. table accelerates).  Its results agree
+   with QMC_FP64 to rounding; a walker whose reference matrix is singular but
+   whose CI sum is not gets finite values here.  It returns QMC_EUNSUPPORTED
+   when the per-walker tables (growing with the number of distinct
+   configurations) exceed the 160 KiB of LDS of a compute unit. */
 typedef enum {
     QMC_FP64 = 0,
     QMC_MIXED_FP32 = 1,
     QMC_MIXED_BF16 = 2,
-    QMC_MIXED_BF16_X1 = 3
+    QMC_MIXED_BF16_X1 = 3,
+    QMC_FP64_EXPLICIT = 4
 } qmc_precision;
 
 /* Radial form of every AO: Slater r^kn exp(-zeta r) or contracted

@@ -24,6 +24,7 @@ hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *d
                        double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param,
                        hipStream_t st);
 size_t grad_lds_bytes(const DevSystem &S);
+size_t explicit_lds_bytes(const DevSystem &S);
 }  // namespace qmc
 
 using qmc::DevSystem;
@@ -313,6 +314,53 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     }
     const int n_det = (int)ci.size();
 
+    // --- distinct spin configurations for the explicit method ----------------
+    std::map<std::vector<int>, int> cfg_id[2];
+    std::vector<std::vector<int>> cfgs[2];
+    std::vector<int2> det_cfg;
+    std::vector<double> ci_x;
+    for (int n = 0; n < d->n_det; ++n) {
+        int id[2];
+        bool repeated = false;
+        for (int s = 0; s < 2; ++s) {
+            const int ns = s == 0 ? nu : nd;
+            const int *occ = s == 0 ? d->occ_up + n * nu : d->occ_dn + n * nd;
+            std::vector<int> c(ns);
+            for (int k = 0; k < ns; ++k) c[k] = new_of_old[occ[k]];
+            std::vector<int> sorted = c;
+            std::sort(sorted.begin(), sorted.end());
+            if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) repeated = true;
+            auto it = cfg_id[s].find(c);
+            if (it == cfg_id[s].end()) {
+                it = cfg_id[s].emplace(c, (int)cfgs[s].size()).first;
+                cfgs[s].push_back(c);
+            }
+            id[s] = it->second;
+        }
+        if (repeated) continue;  // identically zero determinant
+        det_cfg.push_back(make_int2(id[0], id[1]));
+        ci_x.push_back(d->ci[n]);
+    }
+    const int n_cfg_max = (int)std::max(cfgs[0].size(), cfgs[1].size());
+    std::vector<int> cfg_occ(2 * n_cfg_max * qmc::kMaxSpin, 0);
+    for (int s = 0; s < 2; ++s)
+        for (size_t q = 0; q < cfgs[s].size(); ++q)
+            for (size_t k = 0; k < cfgs[s][q].size(); ++k) cfg_occ[(s * n_cfg_max + q) * qmc::kMaxSpin + k] = cfgs[s][q][k];
+    std::vector<int> cfg_off(2 * (n_cfg_max + 1), 0);
+    std::vector<int2> cfg_use;
+    for (int s = 0; s < 2; ++s) {
+        std::vector<std::vector<int2>> use(n_cfg_max);
+        for (size_t n = 0; n < det_cfg.size(); ++n) {
+            const int own = s == 0 ? det_cfg[n].x : det_cfg[n].y, oth = s == 0 ? det_cfg[n].y : det_cfg[n].x;
+            use[own].push_back(make_int2((int)n, oth));
+        }
+        for (int q = 0; q < n_cfg_max; ++q) {
+            cfg_off[s * (n_cfg_max + 1) + q] = (int)cfg_use.size();
+            cfg_use.insert(cfg_use.end(), use[q].begin(), use[q].end());
+        }
+        cfg_off[s * (n_cfg_max + 1) + n_cfg_max] = (int)cfg_use.size();
+    }
+
     // --- cofactor contribution lists: C_s[k][v] = dS / dT_s[k][v] -------------
     // key (spin, k, v) -> contributions (det, sign, h', p'); sign 0 = unit cofactor
     std::map<std::tuple<int, int, int>, std::vector<int4>> ent;
@@ -453,6 +501,11 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     const size_t o_crec = push_bytes(blob, cof_recs.data(), cof_recs.size());
     const size_t o_jen = push_bytes(blob, d->jas_en, d->jas_en ? (size_t)3 * d->n_atoms : 0);
     const size_t o_jeen = push_bytes(blob, d->jas_een, (size_t)7 * d->jas_een_n);
+    const size_t o_cocc = push_bytes(blob, cfg_occ.data(), cfg_occ.size());
+    const size_t o_dcfg = push_bytes(blob, det_cfg.data(), det_cfg.size());
+    const size_t o_cix = push_bytes(blob, ci_x.data(), ci_x.size());
+    const size_t o_coff = push_bytes(blob, cfg_off.data(), cfg_off.size());
+    const size_t o_cuse = push_bytes(blob, cfg_use.data(), cfg_use.size());
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return QMC_EDEVICE;
@@ -511,6 +564,15 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.jas_en = d->jas_en ? (const double *)(base + o_jen) : nullptr;
     S.jas_een = (const double *)(base + o_jeen);
     S.een_n = d->jas_een_n;
+    S.n_cfg_up = (int)cfgs[0].size();
+    S.n_cfg_dn = (int)cfgs[1].size();
+    S.n_cfg_max = n_cfg_max;
+    S.n_det_x = (int)det_cfg.size();
+    S.cfg_occ = (const int *)(base + o_cocc);
+    S.det_cfg = (const int2 *)(base + o_dcfg);
+    S.ci_x = (const double *)(base + o_cix);
+    S.cfg_off = (const int *)(base + o_coff);
+    S.cfg_use = (const int2 *)(base + o_cuse);
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
@@ -531,9 +593,10 @@ void qmc_system_destroy(qmc_system *sys) {
 static qmc_status check_walk_args(qmc_system *sys, int32_t precision, int64_t W) {
     if (!sys) return QMC_EINVAL;
     if (W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
-    if (precision < QMC_FP64 || precision > QMC_MIXED_BF16_X1) return QMC_EINVAL;
+    if (precision < QMC_FP64 || precision > QMC_FP64_EXPLICIT) return QMC_EINVAL;
     if ((precision == QMC_MIXED_BF16 || precision == QMC_MIXED_BF16_X1) && sys->S.n_ao > 32)
         return QMC_EUNSUPPORTED;
+    if (precision == QMC_FP64_EXPLICIT && qmc::explicit_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
     return QMC_OK;
 }
 

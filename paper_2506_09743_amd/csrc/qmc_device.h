@@ -54,6 +54,18 @@ struct DevSystem {
     const double *jas_en;
     const double *jas_een;
     int een_n;
+    // Explicit-determinant method (comparison path): distinct spin
+    // configurations per spin, cfg_occ [2][n_cfg_max][kMaxSpin] internal MO
+    // column per slot; det_cfg [n_det_x] (up config, down config) with the
+    // caller's CI weights ci_x; per configuration the determinants that use
+    // it, cfg_off [2][n_cfg_max + 1] into cfg_use [..] = (det, other-spin
+    // config).
+    int n_cfg_up, n_cfg_dn, n_cfg_max, n_det_x;
+    const int *cfg_occ;
+    const int2 *det_cfg;
+    const double *ci_x;
+    const int *cfg_off;
+    const int2 *cfg_use;
 };
 
 // Largest number of e-e-n terms.

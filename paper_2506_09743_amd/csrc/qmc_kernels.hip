@@ -16,11 +16,11 @@ struct WalkerResult {
 // positions held by its lanes (x0, x1, x2 of the lane's electron).  Every
 // lane of the block must call it (it contains block barriers); results are
 // identical on all lanes of a walker.
-template <int NMO, typename RT, int MF>
+template <int NMO, typename RT, int MF, bool EXPL>
 __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
-                                    double x1, double x2, void *stage) {
+                                                    double x1, double x2, void *stage) {
     Core<NMO> c;
-    core_stages<NMO, RT, MF>(S, L, wsm, x0, x1, x2, c, stage);
+    core_stages<NMO, RT, MF, EXPL>(S, L, wsm, x0, x1, x2, c, stage);
 
     // ---- pass 2: grad and Laplacian of Sigma at this electron ---------------
     double gS0, gS1, gS2, lapS;
@@ -54,14 +54,20 @@ __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const La
     return res;
 }
 
-template <int NMO, typename RT, int MF>
+template <int NMO, bool EXPL>
+__device__ __forceinline__ int lds_per_walker(const DevSystem &S) {
+    if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
+    else return walker_lds<NMO>(S);
+}
+
+template <int NMO, typename RT, int MF, bool EXPL>
 __global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
                                                  double *__restrict__ LP, double *__restrict__ SG,
                                                  double *__restrict__ EL) {
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * walker_lds<NMO>(S);
+    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -69,7 +75,7 @@ __global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__res
         x1 = p[1];
         x2 = p[2];
     }
-    const WalkerResult r = eval_walker<NMO, RT, MF>(S, L, wsm, x0, x1, x2, smem);
+    const WalkerResult r = eval_walker<NMO, RT, MF, EXPL>(S, L, wsm, x0, x1, x2, smem);
     if (L.wvalid && L.lw == 0) {
         LP[w] = r.logpsi;
         SG[w] = r.sign;
@@ -77,7 +83,7 @@ __global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__res
     }
 }
 
-template <int NMO, typename RT, int MF>
+template <int NMO, typename RT, int MF, bool EXPL>
 __global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__restrict__ X,
                                                       double *__restrict__ LP, double *__restrict__ SG,
                                                       double *__restrict__ EL, int64_t W, int n_steps,
@@ -86,7 +92,7 @@ __global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__res
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * walker_lds<NMO>(S);
+    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__res
         const uint64_t bits = ((((uint64_t)ca[0]) << 32) | (uint64_t)ca[1]) >> 11;
         const double u = (double)bits * (1.0 / 9007199254740992.0);
 
-        const WalkerResult r = eval_walker<NMO, RT, MF>(S, L, wsm, y0, y1, y2, smem);
+        const WalkerResult r = eval_walker<NMO, RT, MF, EXPL>(S, L, wsm, y0, y1, y2, smem);
         const bool acc = isfinite(r.logpsi) && (u < exp(2.0 * (r.logpsi - lp)));
         if (acc) {
             x0 = y0;
@@ -175,20 +181,43 @@ static int nmo_bucket(int n_mo) {
 
 int padded_mo(int n_mo) { return nmo_bucket(n_mo); }
 
-template <int NMO, typename RT, int MF>
+template <int NMO, typename RT, int MF, bool EXPL = false>
 static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL,
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
                            uint32_t woff, double *ACC, hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
-    size_t lds = (size_t)S.WPW * walker_lds<NMO>(S) * sizeof(double);
+    size_t lds = (size_t)S.WPW * (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S)) * sizeof(double);
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
     if (mc)
-        hipLaunchKernelGGL((k_metropolis<NMO, RT, MF>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
-                           X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
+        hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL>), dim3((unsigned)blocks), dim3(kWave), lds, st,
+                           S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
     else
-        hipLaunchKernelGGL((k_eval<NMO, RT, MF>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
+        hipLaunchKernelGGL((k_eval<NMO, RT, MF, EXPL>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
                            (const double *)X, W, LP, SG, EL);
     return hipGetLastError();
+}
+
+static hipError_t launch_explicit(bool mc, const DevSystem &S, double *X, double *LP, double *SG,
+                                  double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
+                                  uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
+    switch (S.nmo_pad) {
+#define QMC_CASE(N) \
+    case N: return launch_t<N, double, 0, true>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
+#undef QMC_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t explicit_lds_bytes(const DevSystem &S) {
+    int per = 0;
+    switch (S.nmo_pad) {
+#define QMC_CASE(N) \
+    case N: per = walker_lds_explicit<N>(S); break;
+        QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
+#undef QMC_CASE
+    }
+    return (size_t)S.WPW * per * sizeof(double);
 }
 
 template <typename RT, int MF>
@@ -205,7 +234,8 @@ static hipError_t launch_rt(bool mc, const DevSystem &S, double *X, double *LP, 
 }
 
 // form: 0 FP64, 1 mixed FP32 (VALU), 2 mixed BF16 on the matrix cores with
-// split operands, 3 mixed BF16 single products.
+// split operands, 3 mixed BF16 single products, 4 FP64 with explicit
+// determinants.
 hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, double *LP, double *SG,
                           double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
                           uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
@@ -214,6 +244,7 @@ hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, doub
         case 1: return launch_rt<float, 0>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 2: return launch_rt<float, 3>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 3: return launch_rt<float, 1>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        case 4: return launch_explicit(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
     }
     return hipErrorInvalidValue;
 }

@@ -556,7 +556,11 @@ struct Core {
 // adjoint vector a_e.  Every lane of the block must call it (it contains
 // block barriers).  On return the walker's LDS holds the T tables
 // [2][nmax][NMO] at wsm and the cofactor tables right after them.
-template <int NMO, typename RT, int MF = 0>
+template <int NMO>
+__device__ __forceinline__ void explicit_dets(const DevSystem &S, const Lane &L, double *wsm,
+                                              const double (&phi)[NMO], Core<NMO> &c);
+
+template <int NMO, typename RT, int MF = 0, bool EXPL = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
                                             double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
@@ -681,6 +685,13 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         }
     }
 
+    c.J = J;
+    c.gJ0 = gJ0;
+    c.gJ1 = gJ1;
+    c.gJ2 = gJ2;
+    c.lapJ = lapJ;
+    c.vpot = vpot;
+
     // ---- pass 1: MO values of this electron ------------------------------
     double a[NMO];
     if constexpr (MF > 0) {
@@ -696,6 +707,10 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         mo_values<NMO, RT>(S, x0, x1, x2, phi);
 #pragma unroll
         for (int m = 0; m < NMO; ++m) a[m] = double(phi[m]);
+    }
+    if constexpr (EXPL) {
+        explicit_dets<NMO>(S, L, wsm, a, c);
+        return;
     }
 
     // ---- in-place Gauss-Jordan of the reference matrix across the group --
@@ -840,12 +855,6 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         for (int k = 0; k < JMAX; ++k) av[k] = (k < L.nsig) ? ainv[k] - h[k] : av[k];
     }
 
-    c.J = J;
-    c.gJ0 = gJ0;
-    c.gJ1 = gJ1;
-    c.gJ2 = gJ2;
-    c.lapJ = lapJ;
-    c.vpot = vpot;
     c.slot = slot;
     c.Ssum = Ssum;
     c.logD_up = logD_up;
@@ -853,6 +862,210 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     c.sgn_up = sgn_up;
     c.sgn_dn = sgn_dn;
     c.sing_walker = sing_walker;
+}
+
+// ---- explicit determinants (comparison method) ---------------------------
+// Every distinct spin configuration c of the CI expansion is factorised on
+// its own: A_c[e][k] = phi_{occ_c[k]}(r_e) (rows = electrons of the spin,
+// columns = the configuration's orbital slots) by the same in-place
+// Gauss-Jordan across the spin group as the reference matrix of the
+// low-rank path.  Sigma = sum_n d_n D_up D_dn, and
+// a_e[m] = d log Sigma / d phi_m(r_e) = sum_c W_c (A_c^-1)[k][e] for
+// m = occ_c[k], W_c = (sum over the determinants using c of d_n D_other)
+// D_c / Sigma.  This is the work the low-rank scheme of eq. table avoids:
+// one factorisation per configuration instead of one per spin.
+
+// LDS of one walker for the explicit method (doubles): MO rows [LW][NMO],
+// adjoint rows [LW][NMO], per configuration (log|D|, sign, weight)
+// [2][n_cfg_max][3], inverse table [2][kMaxSpin][kMaxSpin], pivot rows
+// [2][kMaxSpin]; the Jastrow stage's tables and positions come first and
+// are dead by then.
+template <int NMO>
+__host__ __device__ inline int walker_lds_explicit(const DevSystem &S) {
+    const int ex = 2 * S.LW * NMO + 6 * S.n_cfg_max + 2 * kMaxSpin * kMaxSpin + 2 * kMaxSpin;
+    const int js = pos_offset<NMO>(S) + 3 * S.LW;
+    return ex > js ? ex : js;
+}
+
+__device__ __forceinline__ double walker_max(double v, int LW) {
+    for (int off = 1; off < LW; off <<= 1) v = fmax(v, shfl_xor_d(v, off));
+    return v;
+}
+
+// In-place Gauss-Jordan of the group's n x n matrix held as one row per
+// lane (a[k], k < n; entries beyond n are zero).  Pivot columns are
+// overwritten by the inverse exactly as for the reference matrix; slot is
+// the pivot step that consumed this lane's row.  Every lane of the block
+// runs the same nmax steps (block barriers inside).
+__device__ __forceinline__ void group_gauss_jordan(const DevSystem &S, const Lane &L, double (&a)[kMaxSpin],
+                                                   int n, int nmax, bool live, double *piv_row, int &slot,
+                                                   double &dprod, bool &singular) {
+    bool done = !L.active || !live;
+    slot = -1;
+    dprod = 1.0;
+    singular = false;
+#pragma unroll
+    for (int j = 0; j < kMaxSpin; ++j) {
+        if (j >= nmax) break;
+        const bool work = live && j < n;
+        double cand = (work && !done) ? fabs(a[j]) : -1.0;
+        int cl = L.i;
+        for (int off = 1; off < S.G; off <<= 1) {
+            const double oc = shfl_xor_d(cand, off);
+            const int ol = __shfl_xor(cl, off);
+            if (oc > cand || (oc == cand && ol < cl)) {
+                cand = oc;
+                cl = ol;
+            }
+        }
+        const double piv = __shfl(a[j], L.gbase + cl);
+        const bool ok = work && cand > 0.0;
+        if (work && !ok) singular = true;
+        const bool is_piv = ok && L.active && L.i == cl;
+        if (is_piv) {
+#pragma unroll
+            for (int m = 0; m < kMaxSpin; ++m) piv_row[m] = a[m];
+            const double inv = 1.0 / piv;
+#pragma unroll
+            for (int m = 0; m < kMaxSpin; ++m) a[m] *= inv;
+            a[j] = inv;
+            done = true;
+            slot = j;
+        }
+        if (work) dprod *= piv;
+        __syncthreads();
+        if (ok && L.active && !is_piv) {
+            const double f = a[j] / piv;
+#pragma unroll
+            for (int m = 0; m < kMaxSpin; ++m) a[m] -= f * piv_row[m];
+            a[j] = -f;
+        }
+        __syncthreads();
+    }
+}
+
+// Sign of the row permutation (slot s <- electron row) within the group.
+__device__ __forceinline__ double group_parity(const DevSystem &S, const Lane &L, int slot) {
+    int inv_cnt = 0;
+    for (int ip = 0; ip < S.G; ++ip) {
+        const int so = __shfl(slot, L.gbase + ip);
+        if (L.active && ip > L.i && so >= 0 && so < slot) ++inv_cnt;
+    }
+    for (int off = 1; off < S.G; off <<= 1) inv_cnt += __shfl_xor(inv_cnt, off);
+    return (inv_cnt & 1) ? -1.0 : 1.0;
+}
+
+template <int NMO>
+__device__ __forceinline__ void explicit_dets(const DevSystem &S, const Lane &L, double *wsm,
+                                              const double (&phi)[NMO], Core<NMO> &c) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    double *sPhi = wsm;                                   // [LW][NMO]
+    double *sA = sPhi + S.LW * NMO;                       // [LW][NMO]
+    double *sCfg = sA + S.LW * NMO;                       // [2][n_cfg_max][3]
+    double *sInv = sCfg + 6 * S.n_cfg_max;                // [2][kMaxSpin][kMaxSpin]
+    double *sPv = sInv + 2 * kMaxSpin * kMaxSpin;         // [2][kMaxSpin]
+    double *inv_g = sInv + L.grp * kMaxSpin * kMaxSpin;
+    double *piv_g = sPv + L.grp * kMaxSpin;
+    double *cfg_g = sCfg + L.grp * S.n_cfg_max * 3;
+    const int *occ_g = S.cfg_occ + L.grp * S.n_cfg_max * kMaxSpin;
+    const int ncfg_g = L.grp == 0 ? S.n_cfg_up : S.n_cfg_dn;
+    const int ncmax = S.n_cfg_up > S.n_cfg_dn ? S.n_cfg_up : S.n_cfg_dn;
+
+    __syncthreads();  // the Jastrow stage's tables are no longer read
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) {
+        sPhi[L.lw * NMO + m] = phi[m];
+        sA[L.lw * NMO + m] = 0.0;
+    }
+    __syncthreads();
+
+    // pass A: log|D_c| and sign of every configuration of this spin
+    for (int q = 0; q < ncmax; ++q) {
+        const bool live = q < ncfg_g;
+        const int *occ = occ_g + (live ? q : 0) * kMaxSpin;
+        double a[kMaxSpin];
+#pragma unroll
+        for (int k = 0; k < kMaxSpin; ++k)
+            a[k] = (L.active && live && k < L.nsig) ? sPhi[L.lw * NMO + occ[k]] : 0.0;
+        int slot;
+        double dprod;
+        bool singular;
+        group_gauss_jordan(S, L, a, L.nsig, nmax, live, piv_g, slot, dprod, singular);
+        const double par = group_parity(S, L, slot);
+        if (live && L.i == 0) {
+            cfg_g[3 * q] = singular ? -INFINITY : log(fabs(dprod));
+            cfg_g[3 * q + 1] = singular ? 0.0 : par * (dprod < 0.0 ? -1.0 : 1.0);
+        }
+    }
+    __syncthreads();
+
+    // common shifts, Sigma / (e^mu e^md)
+    double mu = -INFINITY, md = -INFINITY;
+    for (int q = L.lw; q < S.n_cfg_up; q += S.LW) mu = fmax(mu, sCfg[3 * q]);
+    for (int q = L.lw; q < S.n_cfg_dn; q += S.LW) md = fmax(md, sCfg[3 * (S.n_cfg_max + q)]);
+    mu = walker_max(mu, S.LW);
+    md = walker_max(md, S.LW);
+    const bool none = mu == -INFINITY || md == -INFINITY;
+    double Sp = 0.0;
+    if (!none)
+        for (int n = L.lw; n < S.n_det_x; n += S.LW) {
+            const int2 dc = S.det_cfg[n];
+            const double *u = sCfg + 3 * dc.x, *v = sCfg + 3 * (S.n_cfg_max + dc.y);
+            Sp += S.ci_x[n] * u[1] * v[1] * exp((u[0] - mu) + (v[0] - md));
+        }
+    const double Ssum = walker_sum(Sp, S.LW);
+    const bool zero = none || Ssum == 0.0 || !isfinite(Ssum);
+
+    // weights W_c (the lanes split both spins' configurations)
+    for (int q = L.lw; q < S.n_cfg_up + S.n_cfg_dn; q += S.LW) {
+        const int sp = q < S.n_cfg_up ? 0 : 1;
+        const int cq = sp ? q - S.n_cfg_up : q;
+        double *own = sCfg + 3 * (sp * S.n_cfg_max + cq);
+        const double m_own = sp ? md : mu, m_oth = sp ? mu : md;
+        double acc = 0.0;
+        const int *off = S.cfg_off + sp * (S.n_cfg_max + 1);
+        for (int t = off[cq]; t < off[cq + 1]; ++t) {
+            const int2 e = S.cfg_use[t];
+            const double *o = sCfg + 3 * ((1 - sp) * S.n_cfg_max + e.y);
+            acc += S.ci_x[e.x] * o[1] * exp(o[0] - m_oth);
+        }
+        own[2] = zero ? 0.0 : acc * own[1] * exp(own[0] - m_own) / Ssum;
+    }
+    __syncthreads();
+
+    // pass B: a_e accumulated from each weighted inverse
+    for (int q = 0; q < ncmax; ++q) {
+        const bool in = q < ncfg_g;
+        const double wq = in ? cfg_g[3 * q + 2] : 0.0;
+        const bool live = in && wq != 0.0;
+        const int *occ = occ_g + (in ? q : 0) * kMaxSpin;
+        double a[kMaxSpin];
+#pragma unroll
+        for (int k = 0; k < kMaxSpin; ++k)
+            a[k] = (L.active && live && k < L.nsig) ? sPhi[L.lw * NMO + occ[k]] : 0.0;
+        int slot;
+        double dprod;
+        bool singular;
+        group_gauss_jordan(S, L, a, L.nsig, nmax, live, piv_g, slot, dprod, singular);
+        if (live && L.active && slot >= 0) {
+#pragma unroll
+            for (int k = 0; k < kMaxSpin; ++k) inv_g[slot * kMaxSpin + k] = a[k];
+        }
+        __syncthreads();
+        if (live && L.active && slot >= 0) {
+            for (int k = 0; k < L.nsig; ++k) sA[L.lw * NMO + occ[k]] += wq * inv_g[k * kMaxSpin + slot];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < NMO; ++m) c.av[m] = sA[L.lw * NMO + m];
+    c.slot = -1;
+    c.Ssum = Ssum;
+    c.logD_up = mu;
+    c.logD_dn = md;
+    c.sgn_up = 1.0;
+    c.sgn_dn = 1.0;
+    c.sing_walker = zero ? 1 : 0;
 }
 
 }  // namespace walker

@@ -16,10 +16,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
 QMC_OK, QMC_EINVAL, QMC_ENOMEM, QMC_EDEVICE, QMC_EUNSUPPORTED = 0, -1, -2, -3, -4
-QMC_FP64, QMC_MIXED_FP32, QMC_MIXED_BF16, QMC_MIXED_BF16_X1 = 0, 1, 2, 3
+QMC_FP64, QMC_MIXED_FP32, QMC_MIXED_BF16, QMC_MIXED_BF16_X1, QMC_FP64_EXPLICIT = 0, 1, 2, 3, 4
 QMC_STO, QMC_GTO = 0, 1
 PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_MIXED_FP32, "bf16": QMC_MIXED_BF16,
-              "bf16x1": QMC_MIXED_BF16_X1}
+              "bf16x1": QMC_MIXED_BF16_X1, "fp64_explicit": QMC_FP64_EXPLICIT}
 
 # every symbol include/qmc.h declares
 EXPORTS = ("qmc_system_create", "qmc_system_destroy", "qmc_eval_psi_eloc", "qmc_metropolis_block",

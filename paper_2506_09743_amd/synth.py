@@ -248,6 +248,58 @@ def make_system(name: str, bond_scale: float = 1.0, seed: int | None = None) -> 
     return MAKERS[name](bond_scale=bond_scale, seed=seed)
 
 
+def with_sd_expansion(sysd: dict, n_active: int, seed: int) -> dict:
+    """A copy of ``sysd`` whose determinant list is SD(n_active, n_active):
+    the reference plus every single and double excitation (total rank <= 2
+    over both spins) of n_active / 2 electrons per spin from the highest
+    occupied orbitals into the n_active / 2 lowest virtual orbitals of that
+    spin.  An excitation replaces the hole's orbital in its slot.  CI weights:
+    1 for the reference, N(0, 0.05^2) for the others."""
+    k = n_active // 2
+    if 2 * k != n_active or k < 1:
+        raise ValueError("n_active must be a positive even number")
+    nu, nd = int(sysd["n_up"]), int(sysd["n_dn"])
+    n_mo = np.asarray(sysd["mo_coef"]).shape[1]
+    if k > min(nu, nd) or max(nu, nd) + k > n_mo:
+        raise ValueError("active space does not fit the orbitals")
+
+    def spin_configs(n):
+        ref = list(range(n))
+        holes = list(range(n - k, n))
+        parts = list(range(n, n + k))
+        out = {0: [ref], 1: [], 2: []}
+        for h in holes:
+            for p in parts:
+                c = ref.copy()
+                c[h] = p
+                out[1].append(c)
+        for h1, h2 in itertools.combinations(holes, 2):
+            for p1, p2 in itertools.combinations(parts, 2):
+                c = ref.copy()
+                c[h1], c[h2] = p1, p2
+                out[2].append(c)
+        return out
+
+    up, dn = spin_configs(nu), spin_configs(nd)
+    occ_up, occ_dn = [], []
+    for ru in (0, 1, 2):
+        for rd in (0, 1, 2):
+            if ru + rd > 2:
+                continue
+            for cu in up[ru]:
+                for cd in dn[rd]:
+                    occ_up.append(cu)
+                    occ_dn.append(cd)
+    rng = np.random.default_rng(seed)
+    ci = rng.normal(0.0, 0.05, len(occ_up))
+    ci[0] = 1.0
+    d = dict(sysd)
+    d["occ_up"] = np.asarray(occ_up, dtype=np.int32).reshape(len(occ_up), nu)
+    d["occ_dn"] = np.asarray(occ_dn, dtype=np.int32).reshape(len(occ_dn), nd)
+    d["ci"] = ci
+    return d
+
+
 MBJ_SEED = {"H2": 2000, "LiH": 2001, "CO": 2002, "Li2": 2003}
 
 
