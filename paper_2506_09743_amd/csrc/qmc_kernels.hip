@@ -60,8 +60,11 @@ __device__ __forceinline__ int lds_per_walker(const DevSystem &S) {
     else return walker_lds<NMO>(S);
 }
 
+// The matrix-core forms ask for two waves per SIMD: left alone the compiler
+// spends a few registers more than that allows and the kernel runs at one.
+// The vector-unit forms are faster with the registers they choose.
 template <int NMO, typename RT, int MF, bool EXPL>
-__global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
+__global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
                                                  double *__restrict__ LP, double *__restrict__ SG,
                                                  double *__restrict__ EL) {
     extern __shared__ double smem[];
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(kWave) void k_eval(DevSystem S, const double *__res
 }
 
 template <int NMO, typename RT, int MF, bool EXPL>
-__global__ __launch_bounds__(kWave) void k_metropolis(DevSystem S, double *__restrict__ X,
+__global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSystem S, double *__restrict__ X,
                                                       double *__restrict__ LP, double *__restrict__ SG,
                                                       double *__restrict__ EL, int64_t W, int n_steps,
                                                       double sigma, uint64_t seed, uint64_t step0,
