@@ -31,19 +31,79 @@
 namespace qmc {
 namespace walker {
 
+// Determinant and cofactor records fetched per batch.
+constexpr int kRecBatch = 4;
 
-__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m); }
 
-// Sum over the LW lanes of a walker (LW a power of two, walkers aligned).
-__device__ __forceinline__ double walker_sum(double v, int LW) {
-    for (int off = 1; off < LW; off <<= 1) v += shfl_xor_d(v, off);
+// Cross-lane exchange within a row of 16 lanes by DPP moves (no LDS round
+// trip).  Walkers (LW <= 16 lanes) and spin groups (G <= 8 lanes) are
+// aligned to their power-of-two size, so these steps never leave them:
+// kSwap1 pairs lane ^ 1 and kSwap2 lane ^ 2 (quad permutes), kHalfMirror
+// pairs lane i with 7 - i in each 8-lane half (the other quad), kMirror
+// pairs lane i with 15 - i (the other half).  Applied in this order a
+// reduction pairs the same partial results as an xor butterfly, and every
+// lane of the span ends with the same value.  Callers run them with all
+// lanes of the wave active.
+constexpr int kSwap1 = 0xB1, kSwap2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    return __hiloint2double(dpp_i<CTRL>(__double2hiint(v)), dpp_i<CTRL>(__double2loint(v)));
+}
+
+// Sum over an aligned span of n = 1, 2, 4, 8 or 16 lanes.
+__device__ __forceinline__ double span_sum(double v, int n) {
+    if (n > 1) v += dpp_d<kSwap1>(v);
+    if (n > 2) v += dpp_d<kSwap2>(v);
+    if (n > 4) v += dpp_d<kHalfMirror>(v);
+    if (n > 8) v += dpp_d<kMirror>(v);
     return v;
 }
 
-__device__ __forceinline__ int walker_sum_i(int v, int LW) {
-    for (int off = 1; off < LW; off <<= 1) v += __shfl_xor(v, off);
+__device__ __forceinline__ int span_sum_i(int v, int n) {
+    if (n > 1) v += dpp_i<kSwap1>(v);
+    if (n > 2) v += dpp_i<kSwap2>(v);
+    if (n > 4) v += dpp_i<kHalfMirror>(v);
+    if (n > 8) v += dpp_i<kMirror>(v);
     return v;
 }
+
+__device__ __forceinline__ double span_max(double v, int n) {
+    if (n > 1) v = fmax(v, dpp_d<kSwap1>(v));
+    if (n > 2) v = fmax(v, dpp_d<kSwap2>(v));
+    if (n > 4) v = fmax(v, dpp_d<kHalfMirror>(v));
+    if (n > 8) v = fmax(v, dpp_d<kMirror>(v));
+    return v;
+}
+
+// Largest cand over the span, ties to the lower index cl; the result is the
+// same on every lane of the span.
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double &cand, int &cl) {
+    const double oc = dpp_d<CTRL>(cand);
+    const int ol = dpp_i<CTRL>(cl);
+    if (oc > cand || (oc == cand && ol < cl)) {
+        cand = oc;
+        cl = ol;
+    }
+}
+
+__device__ __forceinline__ void span_argmax(double &cand, int &cl, int n) {
+    if (n > 1) argmax_step<kSwap1>(cand, cl);
+    if (n > 2) argmax_step<kSwap2>(cand, cl);
+    if (n > 4) argmax_step<kHalfMirror>(cand, cl);
+    if (n > 8) argmax_step<kMirror>(cand, cl);
+}
+
+// Sum over the LW lanes of a walker.
+__device__ __forceinline__ double walker_sum(double v, int LW) { return span_sum(v, LW); }
+
+__device__ __forceinline__ int walker_sum_i(int v, int LW) { return span_sum_i(v, LW); }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -729,15 +789,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         const bool work = j < L.nsig;
         double cand = (work && !done) ? fabs(a[j]) : -1.0;
         int cl = L.i;
-        for (int off = 1; off < S.G; off <<= 1) {
-            const double oc = shfl_xor_d(cand, off);
-            const int ol = __shfl_xor(cl, off);
-            if (oc > cand || (oc == cand && ol < cl)) {
-                cand = oc;
-                cl = ol;
-            }
-        }
-        const double piv = __shfl(a[j], L.gbase + cl);
+        span_argmax(cand, cl, S.G);
         const bool ok = work && cand > 0.0;
         if (work && !ok) singular = true;
         const bool is_piv = ok && L.active && L.i == cl;
@@ -745,15 +797,17 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
             // publish the unscaled pivot row, then scale this row in place
 #pragma unroll
             for (int m = 0; m < NMO; ++m) piv_row[m] = a[m];
-            const double inv = 1.0 / piv;
+            const double inv = 1.0 / a[j];
 #pragma unroll
             for (int m = 0; m < NMO; ++m) a[m] *= inv;
             a[j] = inv;
             done = true;
             slot = j;
         }
-        if (work) dprod *= piv;
         __syncthreads();
+        // the pivot from the published row (a column without one is zero)
+        const double piv = ok ? piv_row[j] : 0.0;
+        if (work) dprod *= piv;
         if (ok && L.active && !is_piv) {
             // multiplier as in Doolittle elimination: equal rows cancel exactly
             const double f = a[j] / piv;
@@ -773,7 +827,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         const int so = __shfl(slot, L.gbase + ip);
         if (L.active && ip > L.i && so >= 0 && so < slot) ++inv_cnt;
     }
-    for (int off = 1; off < S.G; off <<= 1) inv_cnt += __shfl_xor(inv_cnt, off);
+    inv_cnt = span_sum_i(inv_cnt, S.G);
     const double det_sign = ((inv_cnt & 1) ? -1.0 : 1.0) * (dprod < 0.0 ? -1.0 : 1.0);
     const double det_log = log(fabs(dprod));
     // the shared region now becomes the cofactor tables: zero them
@@ -786,11 +840,19 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     const int sing_walker = walker_sum_i(singular ? 1 : 0, S.LW);
 
     // ---- S = sum_n d_n det T_up[H,P] det T_dn[H,P] ----------------------
+    // records are loaded kRecBatch at a time so their latencies overlap
     const double *Tup = sT, *Tdn = sT + tstride;
     double Sp = 0.0;
-    for (int i = 0; i < S.det_rows; ++i) {
-        const uint4 r = S.det_recs[i * S.LW + L.lw];
-        Sp += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(Tup, r.z) * ratio_code<NMO>(Tdn, r.w);
+    for (int i0 = 0; i0 < S.det_rows; i0 += kRecBatch) {
+        uint4 rb[kRecBatch];
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u)
+            rb[u] = i0 + u < S.det_rows ? S.det_recs[(i0 + u) * S.LW + L.lw] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) {
+            const uint4 r = rb[u];
+            Sp += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(Tup, r.z) * ratio_code<NMO>(Tdn, r.w);
+        }
     }
     const double Ssum = walker_sum(Sp, S.LW);
 
@@ -799,17 +861,24 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     // lane) and writes an entry after its last contribution
     {
         double acc = 0.0;
-        for (int i = 0; i < S.cof_rows; ++i) {
-            const uint4 r = S.cof_recs[i * S.LW + L.lw];
-            const int spin = (r.w >> 1) & 1;
-            const double *Ts = spin ? Tdn : Tup, *To = spin ? Tup : Tdn;
-            const uint32_t cc = r.z >> 18;
-            const double tv = Ts[((cc >> 2) & 7) * NMO + (cc >> 5)];
-            const double cof = (cc & 3) == 0 ? 1.0 : ((cc & 3) == 1 ? tv : -tv);
-            acc += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(To, r.z & 0x3FFFFu) * cof;
-            if (r.w & 1u) {
-                sC[spin * tstride + ((r.w >> 2) & 7) * NMO + (r.w >> 5)] = acc;
-                acc = 0.0;
+        for (int i0 = 0; i0 < S.cof_rows; i0 += kRecBatch) {
+            uint4 rb[kRecBatch];
+#pragma unroll
+            for (int u = 0; u < kRecBatch; ++u)
+                rb[u] = i0 + u < S.cof_rows ? S.cof_recs[(i0 + u) * S.LW + L.lw] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < kRecBatch; ++u) {
+                const uint4 r = rb[u];  // an all-zero padding record adds 0 and never flushes
+                const int spin = (r.w >> 1) & 1;
+                const double *Ts = spin ? Tdn : Tup, *To = spin ? Tup : Tdn;
+                const uint32_t cc = r.z >> 18;
+                const double tv = Ts[((cc >> 2) & 7) * NMO + (cc >> 5)];
+                const double cof = (cc & 3) == 0 ? 1.0 : ((cc & 3) == 1 ? tv : -tv);
+                acc += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(To, r.z & 0x3FFFFu) * cof;
+                if (r.w & 1u) {
+                    sC[spin * tstride + ((r.w >> 2) & 7) * NMO + (r.w >> 5)] = acc;
+                    acc = 0.0;
+                }
             }
         }
     }
@@ -887,10 +956,7 @@ __host__ __device__ inline int walker_lds_explicit(const DevSystem &S) {
     return ex > js ? ex : js;
 }
 
-__device__ __forceinline__ double walker_max(double v, int LW) {
-    for (int off = 1; off < LW; off <<= 1) v = fmax(v, shfl_xor_d(v, off));
-    return v;
-}
+__device__ __forceinline__ double walker_max(double v, int LW) { return span_max(v, LW); }
 
 // In-place Gauss-Jordan of the group's n x n matrix held as one row per
 // lane (a[k], k < n; entries beyond n are zero).  Pivot columns are
@@ -910,30 +976,23 @@ __device__ __forceinline__ void group_gauss_jordan(const DevSystem &S, const Lan
         const bool work = live && j < n;
         double cand = (work && !done) ? fabs(a[j]) : -1.0;
         int cl = L.i;
-        for (int off = 1; off < S.G; off <<= 1) {
-            const double oc = shfl_xor_d(cand, off);
-            const int ol = __shfl_xor(cl, off);
-            if (oc > cand || (oc == cand && ol < cl)) {
-                cand = oc;
-                cl = ol;
-            }
-        }
-        const double piv = __shfl(a[j], L.gbase + cl);
+        span_argmax(cand, cl, S.G);
         const bool ok = work && cand > 0.0;
         if (work && !ok) singular = true;
         const bool is_piv = ok && L.active && L.i == cl;
         if (is_piv) {
 #pragma unroll
             for (int m = 0; m < kMaxSpin; ++m) piv_row[m] = a[m];
-            const double inv = 1.0 / piv;
+            const double inv = 1.0 / a[j];
 #pragma unroll
             for (int m = 0; m < kMaxSpin; ++m) a[m] *= inv;
             a[j] = inv;
             done = true;
             slot = j;
         }
-        if (work) dprod *= piv;
         __syncthreads();
+        const double piv = ok ? piv_row[j] : 0.0;
+        if (work) dprod *= piv;
         if (ok && L.active && !is_piv) {
             const double f = a[j] / piv;
 #pragma unroll
@@ -951,7 +1010,7 @@ __device__ __forceinline__ double group_parity(const DevSystem &S, const Lane &L
         const int so = __shfl(slot, L.gbase + ip);
         if (L.active && ip > L.i && so >= 0 && so < slot) ++inv_cnt;
     }
-    for (int off = 1; off < S.G; off <<= 1) inv_cnt += __shfl_xor(inv_cnt, off);
+    inv_cnt = span_sum_i(inv_cnt, S.G);
     return (inv_cnt & 1) ? -1.0 : 1.0;
 }
 
