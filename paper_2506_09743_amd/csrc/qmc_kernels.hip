@@ -125,13 +125,30 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSyste
         const uint64_t step = step0 + (uint64_t)t;
         uint32_t c[4] = {wid, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)L.e};
         philox4x32_10(c, k0, k1);
-        const double u0 = ((double)c[0] + 0.5) * s32, u1 = ((double)c[1] + 0.5) * s32;
-        const double u2 = ((double)c[2] + 0.5) * s32, u3 = ((double)c[3] + 0.5) * s32;
-        const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
-        double s1, c1;
-        sincos(two_pi * u1, &s1, &c1);
-        const double z0 = r0 * c1, z1 = r0 * s1;
-        const double z2 = r1 * cos(two_pi * u3);
+        double z0, z1, z2;
+        if constexpr (sizeof(RT) == sizeof(double)) {
+            const double u0 = ((double)c[0] + 0.5) * s32, u1 = ((double)c[1] + 0.5) * s32;
+            const double u2 = ((double)c[2] + 0.5) * s32, u3 = ((double)c[3] + 0.5) * s32;
+            const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+            double s1, c1;
+            sincos(two_pi * u1, &s1, &c1);
+            z0 = r0 * c1;
+            z1 = r0 * s1;
+            z2 = r1 * cos(two_pi * u3);
+        } else {
+            // the mixed forms draw their normals in FP32 from the same
+            // counters: 24-bit uniforms (w + 1/2) 2^-24, exact in FP32,
+            // never 0 or 1, on a grid symmetric about 1/2
+            const float f24 = 1.0f / 16777216.0f, tpf = 6.28318530717958648f;
+            const float u0 = ((float)(c[0] >> 8) + 0.5f) * f24, u1 = ((float)(c[1] >> 8) + 0.5f) * f24;
+            const float u2 = ((float)(c[2] >> 8) + 0.5f) * f24, u3 = ((float)(c[3] >> 8) + 0.5f) * f24;
+            const float r0 = sqrtf(-2.0f * __logf(u0)), r1 = sqrtf(-2.0f * __logf(u2));
+            float s1, c1;
+            __sincosf(tpf * u1, &s1, &c1);
+            z0 = double(r0 * c1);
+            z1 = double(r0 * s1);
+            z2 = double(r1 * __cosf(tpf * u3));
+        }
         // no FMA contraction: X + sigma z rounds the product, then the sum
         const double y0 = __dadd_rn(x0, __dmul_rn(sigma, z0));
         const double y1 = __dadd_rn(x1, __dmul_rn(sigma, z1));

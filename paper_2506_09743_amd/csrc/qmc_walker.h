@@ -668,36 +668,39 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     __syncthreads();
 
     // ---- Pade e-e Jastrow and Coulomb terms of this electron -------------
+    // The FP64 form evaluates these pair terms in FP64; the mixed forms in
+    // FP32 (RT) from displacements formed in FP64, with FP64 accumulation.
     double J = 0.0, gJ0 = 0.0, gJ1 = 0.0, gJ2 = 0.0, lapJ = 0.0, vpot = 0.0;
     if (L.active) {
         for (int j = 0; j < S.ne; ++j) {
             if (j == L.e) continue;
             const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
-            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const RT d0 = RT(x0 - sPos[3 * lj]), d1 = RT(x1 - sPos[3 * lj + 1]), d2 = RT(x2 - sPos[3 * lj + 2]);
+            const RT r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             const bool same = (j < S.n_up) == (L.e < S.n_up);
-            const double a = same ? S.a_par : S.a_anti;
+            const RT a = RT(same ? S.a_par : S.a_anti), b = RT(S.b);
             // one division gives both 1/r and 1/(1 + b r)
-            const double den = 1.0 + S.b * r;
-            const double q = 1.0 / (r * den);
-            const double rinv = q * den, dinv = q * r;
-            const double k1 = a * dinv * dinv;                      // K'(r)
-            const double k2 = -2.0 * a * S.b * dinv * dinv * dinv;  // K''(r)
-            J += 0.5 * a * r * dinv;
-            gJ0 += k1 * d0 * rinv;
-            gJ1 += k1 * d1 * rinv;
-            gJ2 += k1 * d2 * rinv;
-            lapJ += k2 + 2.0 * k1 * rinv;
-            vpot += 0.5 * rinv;
+            const RT den = RT(1) + b * r;
+            const RT q = RT(1) / (r * den);
+            const RT rinv = q * den, dinv = q * r;
+            const RT k1 = a * dinv * dinv;                    // K'(r)
+            const RT k2 = RT(-2) * a * b * dinv * dinv * dinv;  // K''(r)
+            J += double(RT(0.5) * a * r * dinv);
+            gJ0 += double(k1 * d0 * rinv);
+            gJ1 += double(k1 * d1 * rinv);
+            gJ2 += double(k1 * d2 * rinv);
+            lapJ += double(k2 + RT(2) * k1 * rinv);
+            vpot += double(RT(0.5) * rinv);
         }
         for (int a = 0; a < S.n_atoms; ++a) {
             const double *A = S.atoms + 4 * a;
             const double d0 = x0 - A[0], d1 = x1 - A[1], d2 = x2 - A[2];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            vpot -= A[3] / r;
+            const RT rr = RT(d0 * d0 + d1 * d1 + d2 * d2);
+            vpot -= double(RT(A[3]) / sqrt(rr));
             if (S.jas_en) {
                 // e-n kernel K = N / D, N = w0 r + w1 r^2, D = 1 + w2 r:
                 // K' = (N' - K D') / D and K'' = (N'' - 2 K' D') / D
+                const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
                 const double *w = S.jas_en + 3 * a;
                 const double q = 1.0 / (1.0 + w[2] * r), rinv = 1.0 / r;
                 const double K = (w[0] + w[1] * r) * r * q;
