@@ -78,6 +78,26 @@ def flops_per_walker_step(sysd) -> dict:
     return f
 
 
+def grad_flops_per_walker(sysd) -> dict:
+    """Algorithmic FP operations of one walker's qmc_grad (estimate from the
+    shapes): the forward Psi / E_L evaluation, the forward-mode determinant
+    algebra for the Hessian-vector product, the MO-coefficient outer
+    products of both outputs, the exponent derivatives per primitive and
+    electron, and the AO Hessian / grad-Laplacian contractions per nucleus."""
+    from paper_2506_09743_amd import synth
+    fw = flops_per_walker_step(sysd)
+    ne, nao = synth.n_elec(sysd), synth.n_ao(sysd)
+    nmo = int(np.asarray(sysd["mo_coef"]).shape[1])
+    n_prim = int(np.asarray(sysd["prim_exp"]).size)
+    f = {"forward": fw["total"] - fw["proposal"] - fw["accept"],
+         "forward_mode_dets": fw["lu"] + fw["dets"] + fw["cofactors"] + fw["traces"],
+         "mo_coef": 3 * 2 * ne * nao * nmo,
+         "exponents": ne * n_prim * 30,
+         "nuclei": ne * nao * 40}
+    f["total"] = sum(f.values())
+    return f
+
+
 def hbm_bytes_per_launch(sysd, W: int) -> int:
     """Walker state read and written once per launch: X, log|Psi|, sign, E_L
     and three accumulators, FP64."""
@@ -215,6 +235,44 @@ def many_body_bench(sysd, args, dev, seed) -> dict:
             "mean_energy": float(np.nanmean(acc.cpu().numpy()[:, 0]) / args.steps)}
 
 
+def grad_bench(args, dev) -> dict:
+    """The hand-written adjoint on the Li2 workload (32768 walkers, FP64,
+    all four outputs): walker-gradients/s, ms per call, roofline against
+    the FP64 vector peak on the algorithmic estimate."""
+    import torch
+    from paper_2506_09743_amd import qmc, synth
+    sysd = synth.make_system("Li2")
+    W = synth.CONFIG_WALKERS["Li2"]
+    system = qmc.System(sysd, device=0)
+    X = torch.from_numpy(synth.init_walkers(sysd, W, synth.WALKER_SEED["Li2"])).to(dev)
+    P, A = system.param_count, system.n_atoms
+    outs = [torch.empty((W, P), dtype=torch.float64, device=dev),
+            torch.empty((W, P), dtype=torch.float64, device=dev),
+            torch.empty((W, A, 3), dtype=torch.float64, device=dev),
+            torch.empty((W, A, 3), dtype=torch.float64, device=dev)]
+    qmc.qmc_grad(system.handle, X, *outs)
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        qmc.qmc_grad(system.handle, X, *outs)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    fl = grad_flops_per_walker(sysd)
+    achieved = fl["total"] * W / (ms * 1e-3)
+    out_bytes = W * (2 * P + 2 * 3 * A) * 8 + W * synth.n_elec(sysd) * 3 * 8
+    system.close()
+    return {"workload": f"Li2, {W} walkers, d log|Psi|/d theta, d E_L/d theta ({P} parameters), "
+                        "d log|Psi|/d R, d E_L/d R",
+            "ms_per_call": ms, "walker_gradients_per_s": W / (ms * 1e-3), "dtype": "f64",
+            "flops_per_walker_estimate": fl["total"], "hbm_bytes_per_call": out_bytes,
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                         "hbm_GBps": out_bytes / (ms * 1e-3) / 1e9}}
+
+
 def sd_sweep_bench(args, dev) -> list:
     """Determinant-count sweep on CO, SD(2,2) .. SD(10,10) (4 .. 876
     determinants): E_L evaluation time of the low-rank method and of the
@@ -273,6 +331,7 @@ def main():
                     help="skip the many-body Jastrow (e-n + e-e-n) measurement")
     ap.add_argument("--no-sd-sweep", action="store_true",
                     help="skip the determinant-count sweep (low-rank vs explicit)")
+    ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (qmc_grad) measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests in the serving measurement (0: skip)")
@@ -372,6 +431,7 @@ def main():
     sd_sweep = None
     if not args.no_sd_sweep and args.system == "CO":
         sd_sweep = sd_sweep_bench(args, dev)
+    gradient = None if args.no_grad else grad_bench(args, dev)
 
     fl = flops_per_walker_step(sysd)
     main_form = results["fp64"]
@@ -418,6 +478,7 @@ def main():
         "serving": serving,
         "many_body_jastrow": many_body,
         "determinant_sweep": sd_sweep,
+        "gradient": gradient,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

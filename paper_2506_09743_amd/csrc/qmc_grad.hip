@@ -40,12 +40,28 @@ struct GradOut {
 // tables (Tdot / Ainvdot, Cdot, slot-indexed B0 and Z rows), reused later
 // for the per-electron rows of the MO-coefficient gradient, then positions
 // and the per-atom accumulators.
+// LDS of one walker in the gradient kernel (doubles).  The shared-stage
+// tables (walker_lds, at 0) are followed by the forward-mode tables
+// [3][2][n_max][NMO]; the Jastrow b-derivatives' positions [LW][3] come
+// first in that same space (they are read before the shared stages).  Once
+// a_e and its forward-mode derivative are in registers, all of it is dead
+// and the per-electron rows [LW][2 n_ao + 2 NMO] (chi, beta, a, adot) take
+// the block from 0.  The per-nucleus results [n_atoms][6] live past the end
+// of both.
+template <int NMO>
+__host__ __device__ inline int grad_rows_end(const DevSystem &S) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int base = walker_lds<NMO>(S);
+    const int fwd = base + 6 * nmax * NMO;
+    const int rows = S.LW * (2 * S.n_ao + 2 * NMO);
+    const int pos = base + 3 * S.LW;
+    int e = fwd > rows ? fwd : rows;
+    return e > pos ? e : pos;
+}
+
 template <int NMO>
 __host__ __device__ inline int grad_extra_lds(const DevSystem &S) {
-    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
-    const int t3 = 3 * 2 * nmax * NMO;
-    const int rows = S.LW * (2 * S.n_ao + 2 * NMO);
-    return (t3 > rows ? t3 : rows) + 3 * S.LW + 6 * S.n_atoms;
+    return grad_rows_end<NMO>(S) + 6 * S.n_atoms - walker_lds<NMO>(S);
 }
 
 // Derivative of the k <= 2 minor det T[H,P] along Tdot.
@@ -146,10 +162,9 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
     double *gx = wsm + base_lds;               // gradient-only region
     double *sTD = gx, *sCD = gx + 2 * ts, *sZB = gx + 4 * ts;
     const int rows_len = 2 * S.n_ao + 2 * NMO;
-    const int big = (6 * ts > S.LW * rows_len) ? 6 * ts : S.LW * rows_len;
-    double *sRows = gx;                        // reused after the forward-mode stage
-    double *sPos = gx + big;                   // [LW][3]
-    double *sAtom = sPos + 3 * S.LW;           // [n_atoms][6]: dlogpsi/dR, dE/dR
+    double *sPos = gx;                         // [LW][3], before the shared stages
+    double *sRows = wsm;                       // after the forward-mode stage
+    double *sAtom = wsm + grad_rows_end<NMO>(S);  // [n_atoms][6]: dlogpsi/dR, dE/dR
 
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
