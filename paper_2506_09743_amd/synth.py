@@ -233,6 +233,33 @@ def make_co(bond_scale: float = 1.0, seed: int | None = None) -> dict:
     return _finish(d)
 
 
+def make_max_shape(seed: int | None = None) -> dict:
+    """A synthetic system at the largest shape the kernels are compiled
+    for: two Z = 8 nuclei 2.28 bohr apart, 8 up + 8 down electrons, per atom
+    four s, two p and one Cartesian d shell of contracted GTOs (32 AOs, 2-4
+    primitives per shell, exponents log-uniform in [0.1, 500]), 32 MOs
+    (a sign-fixed 32x32 QR), 60 determinants."""
+    rng = np.random.default_rng(SEED_BASE + 7 if seed is None else seed)
+    sa, sl, sk, sn, pe, pc = [], [], [], [], [], []
+    for atom in range(2):
+        for l in (0, 0, 0, 0, 1, 1, 2):
+            npr = int(rng.integers(2, 5))
+            sa.append(atom)
+            sl.append(l)
+            sk.append(0)
+            sn.append(npr)
+            pe.extend(np.exp(rng.uniform(math.log(0.1), math.log(500.0), size=npr)).tolist())
+            pc.extend(rng.standard_normal(npr).tolist())
+    q = orthogonal(32, rng)
+    occ_up, occ_dn = excitation_dets(8, 8, 32, 60)
+    ci = ci_weights(60, rng)
+    d = dict(name="max-shape", Z=[8.0, 8.0], R=[[0, 0, -1.14], [0, 0, 1.14]],
+             n_up=8, n_dn=8, basis="gto", shell_atom=sa, shell_l=sl, shell_kn=sk,
+             shell_nprim=sn, prim_exp=pe, prim_coef=pc, mo_coef=q,
+             occ_up=occ_up, occ_dn=occ_dn, ci=ci, jas_b=1.0)
+    return _finish(d)
+
+
 MAKERS = {"H2": make_h2, "LiH": make_lih, "Li2": make_li2, "CO": make_co}
 
 # Walker counts and block lengths of the four workloads.

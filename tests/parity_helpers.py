@@ -10,6 +10,8 @@ satisfy |d E_L| <= 1e-12 kappa_S max(1, |E_kin|).
 """
 import numpy as np
 
+from paper_2506_09743_amd import synth
+
 LOG_TOL, E_TOL = 1e-10, 1e-8
 COND_MAX, KAPPA_S_MAX, E_MAX = 1e8, 1e3, 1e4
 
@@ -67,3 +69,31 @@ def _one_step_margin(o, sysd, X, lp, seed, step, sigma, oracle_mod, offset=0):
         d = o.eval_one(X[w] + sigma * z)
         out[w] = abs(2 * (d["logpsi"] - lp[w]) - np.log(u)) if np.isfinite(d["logpsi"]) else np.inf
     return out
+
+
+def good_walkers(o, sysd, n, seed):
+    """Walkers where finite differences are well conditioned: electrons at
+    least 0.3 bohr from nuclei and from each other, reference matrices with
+    condition number < 1e3, a CI sum that cancels by less than 10x."""
+    nu = sysd["n_up"]
+    R = np.asarray(sysd["R"])
+    out = []
+    for x in synth.init_walkers(sysd, 400 * n, seed):
+        if np.linalg.norm(x[:, None] - R[None], axis=-1).min() < 0.3:
+            continue
+        dee = np.linalg.norm(x[:, None] - x[None], axis=-1) + 9 * np.eye(len(x))
+        if dee.min() < 0.3:
+            continue
+        phi = o.mo(x)[:, 0, :]
+        up, dn = phi[:nu], phi[nu:]
+        if max(np.linalg.cond(up[:, sysd["occ_up"][0]]), np.linalg.cond(dn[:, sysd["occ_dn"][0]])) > 1e3:
+            continue
+        t = np.array([c * np.linalg.det(up[:, a]) * np.linalg.det(dn[:, b])
+                      for c, a, b in zip(sysd["ci"], sysd["occ_up"], sysd["occ_dn"])])
+        if np.abs(t).sum() > 10 * abs(t.sum()):
+            continue
+        out.append(x)
+        if len(out) == n:
+            break
+    assert len(out) == n
+    return np.array(out)

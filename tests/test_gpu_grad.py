@@ -14,35 +14,11 @@ import numpy as np
 import pytest
 
 from paper_2506_09743_amd import synth
+from parity_helpers import good_walkers as _good_walkers
 
 pytestmark = pytest.mark.gpu
 
 H = 1e-5
-
-
-def _good_walkers(o, sysd, n, seed):
-    nu = sysd["n_up"]
-    R = np.asarray(sysd["R"])
-    out = []
-    for x in synth.init_walkers(sysd, 400 * n, seed):
-        if np.linalg.norm(x[:, None] - R[None], axis=-1).min() < 0.3:
-            continue
-        dee = np.linalg.norm(x[:, None] - x[None], axis=-1) + 9 * np.eye(len(x))
-        if dee.min() < 0.3:
-            continue
-        phi = o.mo(x)[:, 0, :]
-        up, dn = phi[:nu], phi[nu:]
-        if max(np.linalg.cond(up[:, sysd["occ_up"][0]]), np.linalg.cond(dn[:, sysd["occ_dn"][0]])) > 1e3:
-            continue
-        t = np.array([c * np.linalg.det(up[:, a]) * np.linalg.det(dn[:, b])
-                      for c, a, b in zip(sysd["ci"], sysd["occ_up"], sysd["occ_dn"])])
-        if np.abs(t).sum() > 10 * abs(t.sum()):
-            continue
-        out.append(x)
-        if len(out) == n:
-            break
-    assert len(out) == n
-    return np.array(out)
 
 
 def _perturbed(sysd, kind, idx, h):
