@@ -44,7 +44,7 @@ class _System(C.Structure):
         ("shell_nprim", _ip), ("prim_exp", _dp), ("prim_coef", _dp), ("normalize", C.c_int),
         ("n_mo", C.c_int), ("mo_coef", _dp), ("n_det", C.c_int), ("occ_up", _ip), ("occ_dn", _ip),
         ("ci", _dp), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
-        ("en", _dp), ("een_n", C.c_int), ("een", _dp),
+        ("en", _dp), ("een_n", C.c_int), ("een", _dp), ("bf_omega", C.c_double),
     ]
 
 
@@ -73,6 +73,8 @@ def load_library(path: str):
     L.or_max_threads.restype = C.c_int
     L.or_ao.argtypes = [C.c_void_p, _dp, _dp]
     L.or_mo.argtypes = [C.c_void_p, _dp, _dp]
+    L.or_ao_hessian.argtypes = [C.c_void_p, _dp, _dp]
+    L.or_backflow.argtypes = [C.c_void_p, _dp, _dp]
     L.or_eval_one.argtypes = [C.c_void_p, _dp, C.c_void_p, _dp]
     L.or_eval.argtypes = [C.c_void_p, _dp, C.c_int64, _dp, _dp, _dp, C.c_int]
     L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
@@ -132,6 +134,7 @@ class OracleSystem:
         if een is not None and len(een) > 0:
             s.een_n = int(np.asarray(een).shape[0])
             s.een = f64("jas_een")
+        s.bf_omega = float(sysd.get("bf_omega") or 0.0)
         self._keep = keep
         self.s = s
         self.ref = C.byref(s)
@@ -144,6 +147,19 @@ class OracleSystem:
         r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(3))
         out = np.zeros((self.n_ao, 5))
         self.L.or_ao(self.ref, _p(r), _p(out))
+        return out
+
+    def ao_hessian(self, r) -> np.ndarray:
+        """[n_ao][10]: value, dx, dy, dz, xx, xy, xz, yy, yz, zz."""
+        r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(3))
+        out = np.zeros((self.n_ao, 10))
+        self.L.or_ao_hessian(self.ref, _p(r), _p(out))
+        return out
+
+    def backflow(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(self.n_elec, 3))
+        out = np.zeros((self.n_elec, 3))
+        self.L.or_backflow(self.ref, _p(x), _p(out))
         return out
 
     def mo(self, x) -> np.ndarray:

@@ -8,8 +8,15 @@
  * What it computes, with the paper passage each part follows:
  *   - Hamiltonian: kinetic -1/2 sum_i lap_i, e-e repulsion, e-n attraction,
  *     n-n repulsion (Introduction, eq. Hmol), atomic units.
- *   - Wavefunction Psi = exp(J) * sum_n d_n D_n^up D_n^dn (Methods, eq. psimol)
- *     without backflow, so the orbitals see the bare electron positions.
+ *   - Wavefunction Psi = exp(J) * sum_n d_n D_n^up D_n^dn (Methods, eq. psimol).
+ *     Without backflow the orbitals see the bare electron positions; with
+ *     the inverse backflow (Methods, backflow transformation; kernel
+ *     omega / r_ij of the Results section) they see q_i = r_i + sum_{j != i}
+ *     (omega / r_ij) (r_i - r_j), every determinant depends on every
+ *     electron, and its diagonal Hessian follows eq. nabla_d, evaluated
+ *     coordinate by coordinate with dA and d2A from the chain rule through
+ *     q(r) (AO Hessians included).  The Jastrow factor and the potential
+ *     keep the bare positions.
  *   - Slater AOs N x^kx y^ky z^kz r^kn exp(-zeta r) (Methods, AO layer) and
  *     contracted Cartesian Gaussians; closed-form gradient and Laplacian.
  *   - MOs phi_k = sum_mu C[mu][k] chi_mu (Methods, MO layer; C = c*mu).
@@ -19,7 +26,8 @@
  *     Tr(A^-1 lap A) (Appendix on the single-determinant simplification,
  *     eq. claudia_trace); grad Sigma and lap Sigma from eqs. nabla_sigma and
  *     delta_sigma, whose cross term vanishes without backflow because the up
- *     and down determinants depend on disjoint electrons.
+ *     and down determinants depend on disjoint electrons, and is kept with
+ *     it.
  *   - Pade e-e Jastrow K = a r / (1 + b r), a = 1/4 parallel, 1/2
  *     antiparallel (Appendix on additional ansatze, eq. pade_kernel), summed
  *     over pairs i<j (eq. jastrow, e-e term); optionally the many-body
@@ -146,6 +154,132 @@ void or_ao(const or_system *s, const double r[3], double *out) {
     }
 }
 
+/* x^a y^b z^c and its first and second derivatives. */
+static double mono(const double d[3], int a, int b, int c) {
+    return ipow(d[0], a) * ipow(d[1], b) * ipow(d[2], c);
+}
+
+/* AO Hessian by the product rule on chi = P(d) R(r):
+   d_a d_b chi = R d_a d_b P + (d_a P d_b + d_b P d_a) R'/r
+                 + P (delta_ab R'/r + (R'' - R'/r) d_a d_b / r^2),
+   with R' and R'' summed over the primitives (Slater f = r^kn e^{-zeta r}:
+   f' = (kn/r - zeta) f, f'' = ((kn/r - zeta)^2 - kn/r^2) f; Gaussian
+   f = e^{-alpha r^2}: f' = -2 alpha r f, f'' = (4 alpha^2 r^2 - 2 alpha) f). */
+void or_ao_hessian(const or_system *s, const double r[3], double *out) {
+    int mu = 0, p0 = 0;
+    static const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int sh = 0; sh < s->n_shells; ++sh) {
+        const int at = s->shell_atom[sh], l = s->shell_l[sh], kn = s->shell_kn[sh];
+        const int np = s->shell_nprim[sh];
+        const double d[3] = {r[0] - s->R[3 * at], r[1] - s->R[3 * at + 1], r[2] - s->R[3 * at + 2]};
+        const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double R0 = 0.0, R1 = 0.0, R2 = 0.0; /* R, R', R'' */
+        for (int p = 0; p < np; ++p) {
+            const double e = s->prim_exp[p0 + p];
+            const double c = s->prim_coef[p0 + p] * rad_norm(s, l, kn, e);
+            if (s->basis == 0) {
+                const double f = ipow(rr, kn) * exp(-e * rr);
+                const double g = kn / rr - e;
+                R0 += c * f;
+                R1 += c * f * g;
+                R2 += c * f * (g * g - kn / (rr * rr));
+            } else {
+                const double f = exp(-e * rr * rr);
+                R0 += c * f;
+                R1 += c * f * (-2.0 * e * rr);
+                R2 += c * f * (4.0 * e * e * rr * rr - 2.0 * e);
+            }
+        }
+        p0 += np;
+        const double q = R1 / rr, w = (R2 - q) / (rr * rr);
+        for (int a = l; a >= 0; --a) {
+            for (int b = l - a; b >= 0; --b) {
+                const int c = l - a - b;
+                const int e3[3] = {a, b, c};
+                const double f = ang_norm(s, a, b, c);
+                const double P = mono(d, a, b, c);
+                double dP[3];
+                for (int k = 0; k < 3; ++k) {
+                    int ee[3] = {a, b, c};
+                    dP[k] = ee[k] * mono(d, ee[0] - (k == 0), ee[1] - (k == 1), ee[2] - (k == 2));
+                }
+                double *o = out + 10 * mu;
+                o[0] = f * P * R0;
+                for (int k = 0; k < 3; ++k) o[1 + k] = f * (R0 * dP[k] + P * q * d[k]);
+                for (int t = 0; t < 6; ++t) {
+                    const int x1 = ia[t], x2 = ib[t];
+                    int ee[3] = {e3[0], e3[1], e3[2]};
+                    double ddP;
+                    if (x1 == x2) {
+                        ddP = ee[x1] * (ee[x1] - 1) *
+                              mono(d, ee[0] - 2 * (x1 == 0), ee[1] - 2 * (x1 == 1), ee[2] - 2 * (x1 == 2));
+                    } else {
+                        ddP = ee[x1] * ee[x2] *
+                              mono(d, ee[0] - (x1 == 0) - (x2 == 0), ee[1] - (x1 == 1) - (x2 == 1),
+                                   ee[2] - (x1 == 2) - (x2 == 2));
+                    }
+                    const double dRR = (x1 == x2 ? q : 0.0) + w * d[x1] * d[x2];
+                    o[4 + t] = f * (R0 * ddP + q * (dP[x1] * d[x2] + dP[x2] * d[x1]) + P * dRR);
+                }
+                ++mu;
+            }
+        }
+    }
+}
+
+/* Inverse backflow (Methods, backflow transformation, with the kernel
+   K_BF(r) = omega / r of the Results section): q_i = r_i + sum_{j != i}
+   (omega / r_ij) (r_i - r_j). */
+void or_backflow(const or_system *s, const double *x, double *q) {
+    const int ne = s->n_up + s->n_dn;
+    for (int i = 0; i < ne; ++i) {
+        for (int c = 0; c < 3; ++c) q[3 * i + c] = x[3 * i + c];
+        for (int j = 0; j < ne; ++j) {
+            if (j == i) continue;
+            double u[3];
+            for (int c = 0; c < 3; ++c) u[c] = x[3 * i + c] - x[3 * j + c];
+            const double r = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int c = 0; c < 3; ++c) q[3 * i + c] += s->bf_omega / r * u[c];
+        }
+    }
+}
+
+/* First and second derivatives of the backflow map, J[b][a] = dq_b / dx_a
+   and K[b][a] = d^2 q_b / dx_a^2, b and a over the 3 N_e coordinates.  Each
+   pair term T(u) = eta(|u|) u, u = r_i - r_k, eta = omega / r, has
+   dT_b/du_a = eta delta_ab + eta' u_a u_b / r and
+   d^2 T_b / du_a^2 = eta'' u_a^2 u_b / r^2
+                      + eta' (u_b / r - u_a^2 u_b / r^3 + 2 delta_ab u_a / r);
+   it enters q_i with du/dr_i = +1 and du/dr_k = -1. */
+static void backflow_derivs(const or_system *s, const double *x, double *Jm, double *Km) {
+    const int ne = s->n_up + s->n_dn, n3 = 3 * ne;
+    const double om = s->bf_omega;
+    for (int t = 0; t < n3 * n3; ++t) { Jm[t] = 0.0; Km[t] = 0.0; }
+    for (int b = 0; b < n3; ++b) Jm[b * n3 + b] = 1.0;
+    for (int i = 0; i < ne; ++i) {
+        for (int k = 0; k < ne; ++k) {
+            if (k == i) continue;
+            double u[3];
+            for (int c = 0; c < 3; ++c) u[c] = x[3 * i + c] - x[3 * k + c];
+            const double r = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            const double eta = om / r, e1 = -om / (r * r), e2 = 2.0 * om / (r * r * r);
+            for (int bb = 0; bb < 3; ++bb) {
+                for (int aa = 0; aa < 3; ++aa) {
+                    const double d1 = eta * (aa == bb) + e1 * u[aa] * u[bb] / r;
+                    const double d2 = e2 * u[aa] * u[aa] * u[bb] / (r * r) +
+                                      e1 * (u[bb] / r - u[aa] * u[aa] * u[bb] / (r * r * r) +
+                                            2.0 * (aa == bb) * u[aa] / r);
+                    const int row = 3 * i + bb;
+                    Jm[row * n3 + 3 * i + aa] += d1;
+                    Jm[row * n3 + 3 * k + aa] -= d1;
+                    Km[row * n3 + 3 * i + aa] += d2;
+                    Km[row * n3 + 3 * k + aa] += d2;
+                }
+            }
+        }
+    }
+}
+
 void or_mo(const or_system *s, const double *x, double *out) {
     const int ne = s->n_up + s->n_dn, nao = or_n_ao(s), nmo = s->n_mo;
     double *ao = (double *)malloc(sizeof(double) * 5 * nao);
@@ -245,29 +379,142 @@ static int det_block(int n, int e0, int nmo, const double *phi, const int *occ, 
     return 1;
 }
 
+/* One spin block of one determinant with backflow.  phi = MO table at the
+   transformed positions [N_e][10][n_mo] (value, gradient, Hessian).  For
+   every coordinate a of every electron, dA and d2A follow from the chain
+   rule through q(x), and eq. nabla_d gives d^2 D / D = Tr(A^-1 d2A) +
+   Tr(A^-1 dA)^2 - Tr(A^-1 dA A^-1 dA).  Outputs log|D|, sign, g[3 N_e] =
+   d log D / dx_a and lap = sum_a d^2 D / D.  Returns 0 when A is singular. */
+static int det_block_bf(int n, int e0, int ne, int nmo, const double *phi, const int *occ,
+                        const double *Jm, const double *Km, double *work, int *piv, double *logabs,
+                        double *sgn, double *g, double *lap) {
+    const int n3 = 3 * ne;
+    static const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+    if (n == 0) {
+        *logabs = 0.0; *sgn = 1.0; *lap = 0.0;
+        for (int a = 0; a < n3; ++a) g[a] = 0.0;
+        return 1;
+    }
+    double *A = work, *inv = A + n * n, *b = inv + n * n, *dA = b + n, *d2A = dA + n * n, *M = d2A + n * n;
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) A[i * n + k] = phi[((e0 + i) * 10 + 0) * nmo + occ[k]];
+    double ps;
+    if (!lu_factor(n, A, piv, &ps)) return 0;
+    double la = 0.0, sg = ps;
+    for (int k = 0; k < n; ++k) {
+        la += log(fabs(A[k * n + k]));
+        if (A[k * n + k] < 0) sg = -sg;
+    }
+    lu_inverse(n, A, piv, inv, b);
+    double L = 0.0;
+    for (int a = 0; a < n3; ++a) {
+        for (int i = 0; i < n; ++i) {
+            const double *Jr[3], *Kr[3];
+            for (int bb = 0; bb < 3; ++bb) {
+                Jr[bb] = Jm + (size_t)(3 * (e0 + i) + bb) * n3;
+                Kr[bb] = Km + (size_t)(3 * (e0 + i) + bb) * n3;
+            }
+            for (int k = 0; k < n; ++k) {
+                const double *ph = phi + (size_t)(e0 + i) * 10 * nmo + occ[k];
+                double v1 = 0.0, v2 = 0.0;
+                for (int bb = 0; bb < 3; ++bb) {
+                    v1 += ph[(1 + bb) * nmo] * Jr[bb][a];
+                    v2 += ph[(1 + bb) * nmo] * Kr[bb][a];
+                }
+                for (int t = 0; t < 6; ++t) {
+                    const double h = ph[(4 + t) * nmo];
+                    const double jj = Jr[ia[t]][a] * Jr[ib[t]][a];
+                    v2 += (ia[t] == ib[t] ? 1.0 : 2.0) * h * jj;
+                }
+                dA[i * n + k] = v1;
+                d2A[i * n + k] = v2;
+            }
+        }
+        /* M = A^-1 dA; traces */
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j) {
+                double m = 0.0;
+                for (int i = 0; i < n; ++i) m += inv[k * n + i] * dA[i * n + j];
+                M[k * n + j] = m;
+            }
+        for (int k = 0; k < n; ++k) {
+            t2 += M[k * n + k];
+            double m2 = 0.0;
+            for (int i = 0; i < n; ++i) m2 += inv[k * n + i] * d2A[i * n + k];
+            t1 += m2;
+            for (int j = 0; j < n; ++j) t3 += M[k * n + j] * M[j * n + k];
+        }
+        g[a] = t2;
+        L += t1 + t2 * t2 - t3;
+    }
+    *logabs = la; *sgn = sg; *lap = L;
+    return 1;
+}
+
 void or_eval_one(const or_system *s, const double *x, or_detail *out, double *grad) {
     const int nu = s->n_up, nd = s->n_dn, ne = nu + nd, nmo = s->n_mo, nd_ = s->n_det;
     const int nmax = nu > nd ? nu : nd;
-    double *phi = (double *)malloc(sizeof(double) * ne * 5 * nmo);
-    double *work = (double *)malloc(sizeof(double) * (2 * nmax * nmax + nmax + 1));
+    const int bf = s->bf_omega != 0.0, n3 = 3 * ne;
+    double *phi = (double *)malloc(sizeof(double) * ne * (bf ? 10 : 5) * nmo);
+    double *work = (double *)malloc(sizeof(double) * (5 * nmax * nmax + nmax + 1));
     int *piv = (int *)malloc(sizeof(int) * (nmax + 1));
     double *lg = (double *)malloc(sizeof(double) * nd_);       /* log|D_up D_dn| */
     double *sg = (double *)malloc(sizeof(double) * nd_);
     double *ok = (double *)malloc(sizeof(double) * nd_);
     double *gd = (double *)malloc(sizeof(double) * nd_ * (3 * ne + 1)); /* grad log D, lap */
-    or_mo(s, x, phi);
+    double *Jm = NULL, *Km = NULL, *gu = NULL, *gw = NULL;
+    if (bf) {
+        /* MO value, gradient and Hessian at the transformed positions. */
+        const int nao = or_n_ao(s);
+        double *q = (double *)malloc(sizeof(double) * n3);
+        double *ao = (double *)malloc(sizeof(double) * 10 * nao);
+        or_backflow(s, x, q);
+        for (int e = 0; e < ne; ++e) {
+            or_ao_hessian(s, q + 3 * e, ao);
+            for (int c = 0; c < 10; ++c)
+                for (int k = 0; k < nmo; ++k) {
+                    double acc = 0.0;
+                    for (int m = 0; m < nao; ++m) acc += ao[10 * m + c] * s->mo_coef[m * nmo + k];
+                    phi[(e * 10 + c) * nmo + k] = acc;
+                }
+        }
+        free(ao);
+        free(q);
+        Jm = (double *)malloc(sizeof(double) * n3 * n3);
+        Km = (double *)malloc(sizeof(double) * n3 * n3);
+        gu = (double *)malloc(sizeof(double) * n3);
+        gw = (double *)malloc(sizeof(double) * n3);
+        backflow_derivs(s, x, Jm, Km);
+    } else {
+        or_mo(s, x, phi);
+    }
 
     int n_singular = 0;
     for (int n = 0; n < nd_; ++n) {
         double la_u, sg_u, lp_u, la_d, sg_d, lp_d;
         double *g = gd + (size_t)n * (3 * ne + 1);
-        int ou = det_block(nu, 0, nmo, phi, s->occ_up + n * nu, work, piv, &la_u, &sg_u, g, &lp_u);
-        int od = det_block(nd, nu, nmo, phi, s->occ_dn + n * nd, work, piv, &la_d, &sg_d, g + 3 * nu, &lp_d);
+        int ou, od;
+        if (bf) {
+            ou = det_block_bf(nu, 0, ne, nmo, phi, s->occ_up + n * nu, Jm, Km, work, piv, &la_u, &sg_u, gu, &lp_u);
+            od = det_block_bf(nd, nu, ne, nmo, phi, s->occ_dn + n * nd, Jm, Km, work, piv, &la_d, &sg_d, gw, &lp_d);
+        } else {
+            ou = det_block(nu, 0, nmo, phi, s->occ_up + n * nu, work, piv, &la_u, &sg_u, g, &lp_u);
+            od = det_block(nd, nu, nmo, phi, s->occ_dn + n * nd, work, piv, &la_d, &sg_d, g + 3 * nu, &lp_d);
+        }
         ok[n] = (ou && od) ? 1.0 : 0.0;
         if (!(ou && od)) { ++n_singular; lg[n] = -INFINITY; sg[n] = 0.0; continue; }
         lg[n] = la_u + la_d;
         sg[n] = sg_u * sg_d;
         g[3 * ne] = lp_u + lp_d;
+        if (bf) {
+            /* eq. delta_sigma: both spin blocks depend on every electron, so
+               the cross term 2 grad D_up / D_up . grad D_dn / D_dn stays. */
+            for (int a = 0; a < n3; ++a) {
+                g[a] = gu[a] + gw[a];
+                g[3 * ne] += 2.0 * gu[a] * gw[a];
+            }
+        }
     }
     /* Sigma = sum_n d_n D_n^up D_n^dn, shifted by the largest |D| product. */
     double lmax = -INFINITY;
@@ -410,6 +657,7 @@ void or_eval_one(const or_system *s, const double *x, or_detail *out, double *gr
     if (grad)
         for (int q = 0; q < 3 * ne; ++q) grad[q] = gJ[q] + gS[q];
     free(gJ); free(gS); free(gd); free(ok); free(sg); free(lg); free(piv); free(work); free(phi);
+    free(Jm); free(Km); free(gu); free(gw);
 }
 
 int or_max_threads(void) {

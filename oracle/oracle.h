@@ -39,6 +39,7 @@ typedef struct {
                                  per nucleus; NULL: no e-n term */
     int een_n;                /* terms of the e-e-n kernel; 0: none */
     const double *een;        /* [een_n][7]: c, a1, b1, a2, b2, a3, b3 */
+    double bf_omega;          /* inverse backflow kernel omega / r_ij; 0: none */
 } or_system;
 
 /* Per-walker detail of one evaluation. */
@@ -54,6 +55,13 @@ double or_nuclear_repulsion(const or_system *s);
 
 /* AO value, d/dx, d/dy, d/dz, Laplacian at one point: out[n_ao][5]. */
 void or_ao(const or_system *s, const double r[3], double *out);
+
+/* AO value, gradient and Hessian at one point: out[n_ao][10] = value, dx, dy,
+   dz, xx, xy, xz, yy, yz, zz. */
+void or_ao_hessian(const or_system *s, const double r[3], double *out);
+
+/* Backflow-transformed positions q[N_e][3] of x[N_e][3]. */
+void or_backflow(const or_system *s, const double *x, double *q);
 
 /* MO values of every electron: out[N_e][5][n_mo] (value, dx, dy, dz, lap). */
 void or_mo(const or_system *s, const double *x, double *out);
