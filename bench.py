@@ -32,7 +32,8 @@ PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
 PEAK_HBM = 8.0e12          # bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "co_metropolis_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_09743_amd", "csrc", f)
-                  for f in ("qmc_kernels.hip", "qmc_walker.h", "qmc_device.h", "qmc_api.hip")]
+                  for f in ("qmc_kernels.hip", "qmc_walker.h", "qmc_backflow.h", "qmc_device.h",
+                            "qmc_api.hip")]
 
 
 def flops_per_walker_step(sysd) -> dict:

@@ -5,9 +5,11 @@
  * Neural Components for Energy and Force Calculations"):
  *   - the molecular Hamiltonian of the Introduction (eq. Hmol), atomic units;
  *   - the Slater-Jastrow wavefunction Psi = exp(J) sum_n d_n D_n^up D_n^dn
- *     of the Methods section (eq. psimol) without backflow, with Slater or
- *     contracted Cartesian Gaussian AOs (AO layer), MOs phi = sum C chi (MO
- *     layer, C = c * mu), and the e-e Pade Jastrow of eq. pade_kernel;
+ *     of the Methods section (eq. psimol), with Slater or contracted
+ *     Cartesian Gaussian AOs (AO layer), MOs phi = sum C chi (MO layer,
+ *     C = c * mu), the e-e Pade Jastrow of eq. pade_kernel, and optionally
+ *     the inverse backflow transformation (Methods; kernel omega / r_ij of
+ *     the Results section) whose local energy follows eq. nabla_d;
  *   - the local energy E_L = H Psi / Psi with the kinetic split of the
  *     appendix on local energies, the Jacobi-trace derivatives of
  *     eq. claudia_trace and the excited-determinant update of eq. table;
@@ -64,7 +66,10 @@ typedef enum {
    with QMC_FP64 to rounding; a walker whose reference matrix is singular but
    whose CI sum is not gets finite values here.  It returns QMC_EUNSUPPORTED
    when the per-walker tables (growing with the number of distinct
-   configurations) exceed the 160 KiB of LDS of a compute unit. */
+   configurations) exceed the 160 KiB of LDS of a compute unit.
+   With backflow (bf_omega != 0) only FP64 exists: QMC_FP64 and
+   QMC_FP64_EXPLICIT both run the explicit per-configuration evaluation of
+   eq. nabla_d, and the mixed forms return QMC_EUNSUPPORTED. */
 typedef enum {
     QMC_FP64 = 0,
     QMC_MIXED_FP32 = 1,
@@ -109,6 +114,15 @@ typedef struct {
     const double *jas_en;       /* [n_atoms][3] (w0, w1, w2), or NULL: no e-n term */
     int32_t jas_een_n;          /* e-e-n terms, 0..8 (0: none) */
     const double *jas_een;      /* [jas_een_n][7] (c, a1, b1, a2, b2, a3, b3) */
+    /* Inverse backflow (Methods, backflow transformation; kernel of the
+       Results section): the orbitals are evaluated at
+       q_i = r_i + sum_{j != i} (bf_omega / r_ij) (r_i - r_j), the Jastrow
+       factor and the potential at the bare positions.  0: no backflow.
+       With backflow every determinant depends on every electron; E_L then
+       uses eq. nabla_d per spin block and the cross term of eq. delta_sigma,
+       with every distinct spin configuration factorised explicitly (at most
+       128 per spin). */
+    double bf_omega;
 } qmc_system_desc;
 
 typedef struct qmc_system qmc_system;
@@ -159,8 +173,9 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
      d_deloc_dR     [W][n_atoms][3]  d E_L / d R_alpha (includes V_nn)
    Any output may be NULL; at least one must not be.  d_X as in
    qmc_eval_psi_eloc.  Returns QMC_EUNSUPPORTED when the walker tables do not
-   fit the 160 KiB of LDS of a compute unit, and for systems with many-body
-   Jastrow terms (their parameters have no slot in theta). */
+   fit the 160 KiB of LDS of a compute unit, for systems with many-body
+   Jastrow terms (their parameters have no slot in theta) and for systems
+   with backflow. */
 qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
                     double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream);
 

@@ -25,6 +25,7 @@ hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *d
                        hipStream_t st);
 size_t grad_lds_bytes(const DevSystem &S);
 size_t explicit_lds_bytes(const DevSystem &S);
+size_t backflow_lds_bytes(const DevSystem &S);
 }  // namespace qmc
 
 using qmc::DevSystem;
@@ -187,6 +188,7 @@ qmc_status validate(const qmc_system_desc *d) {
             const double v = d->jas_een[7 * m + k];
             if (!is_finite(v) || ((k == 2 || k == 4 || k == 6) && v < 0.0)) return QMC_EINVAL;
         }
+    if (!is_finite(d->bf_omega)) return QMC_EINVAL;
     return QMC_OK;
 }
 
@@ -573,6 +575,7 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.ci_x = (const double *)(base + o_cix);
     S.cfg_off = (const int *)(base + o_coff);
     S.cfg_use = (const int2 *)(base + o_cuse);
+    S.bf_omega = d->bf_omega;
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
@@ -596,8 +599,20 @@ static qmc_status check_walk_args(qmc_system *sys, int32_t precision, int64_t W)
     if (precision < QMC_FP64 || precision > QMC_FP64_EXPLICIT) return QMC_EINVAL;
     if ((precision == QMC_MIXED_BF16 || precision == QMC_MIXED_BF16_X1) && sys->S.n_ao > 32)
         return QMC_EUNSUPPORTED;
+    if (sys->S.bf_omega != 0.0) {
+        // backflow: FP64 only, explicit configurations
+        if (precision != QMC_FP64 && precision != QMC_FP64_EXPLICIT) return QMC_EUNSUPPORTED;
+        if (sys->S.n_cfg_max > qmc::kMaxCfgBF || qmc::backflow_lds_bytes(sys->S) > 160 * 1024)
+            return QMC_EUNSUPPORTED;
+        return QMC_OK;
+    }
     if (precision == QMC_FP64_EXPLICIT && qmc::explicit_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
     return QMC_OK;
+}
+
+// Kernel form of a call: the precision, or 5 for the backflow evaluation.
+static int walk_form(const qmc_system *sys, int32_t precision) {
+    return sys->S.bf_omega != 0.0 ? 5 : precision;
 }
 
 qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d_X, int64_t W,
@@ -608,7 +623,7 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
     if (!d_X || !d_logpsi || !d_sign || !d_eloc) return QMC_EINVAL;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
-    hipError_t e = qmc::launch_walkers(false, precision, sys->S, (double *)d_X,
+    hipError_t e = qmc::launch_walkers(false, walk_form(sys, precision), sys->S, (double *)d_X,
                                        d_logpsi, d_sign, d_eloc, W, 0, 0.0, 0, 0, 0, nullptr,
                                        (hipStream_t)stream);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
@@ -626,7 +641,7 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
     if (!d_X || !d_logpsi || !d_sign || !d_eloc || !d_acc) return QMC_EINVAL;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
-    hipError_t e = qmc::launch_walkers(true, precision, sys->S, d_X, d_logpsi,
+    hipError_t e = qmc::launch_walkers(true, walk_form(sys, precision), sys->S, d_X, d_logpsi,
                                        d_sign, d_eloc, W, n_steps, sigma, seed, step0, walker_offset,
                                        d_acc, (hipStream_t)stream);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
@@ -638,7 +653,7 @@ qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlo
     if (W == 0) return QMC_OK;
     if (!d_X || (!d_dlogpsi && !d_deloc_dtheta && !d_dlogpsi_dR && !d_deloc_dR)) return QMC_EINVAL;
     if (qmc::grad_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
-    if (sys->S.jas_en || sys->S.een_n > 0) return QMC_EUNSUPPORTED;
+    if (sys->S.jas_en || sys->S.een_n > 0 || sys->S.bf_omega != 0.0) return QMC_EUNSUPPORTED;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
     hipError_t e = qmc::launch_grad(sys->S, d_X, W, d_dlogpsi, d_deloc_dtheta, d_dlogpsi_dR, d_deloc_dR,

@@ -66,9 +66,13 @@ struct DevSystem {
     const double *ci_x;
     const int *cfg_off;
     const int2 *cfg_use;
+    // Inverse backflow kernel omega / r_ij (0: none).
+    double bf_omega;
 };
 
 // Largest number of e-e-n terms.
 constexpr int kMaxEen = 8;
+// Largest number of distinct spin configurations per spin with backflow.
+constexpr int kMaxCfgBF = 128;
 
 }  // namespace qmc

@@ -16,15 +16,22 @@ struct WalkerResult {
 // positions held by its lanes (x0, x1, x2 of the lane's electron).  Every
 // lane of the block must call it (it contains block barriers); results are
 // identical on all lanes of a walker.
-template <int NMO, typename RT, int MF, bool EXPL>
+template <int NMO, typename RT, int MF, bool EXPL, bool BF>
 __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
                                                     double x1, double x2, void *stage) {
     Core<NMO> c;
-    core_stages<NMO, RT, MF, EXPL>(S, L, wsm, x0, x1, x2, c, stage);
+    core_stages<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, c, stage);
 
     // ---- pass 2: grad and Laplacian of Sigma at this electron ---------------
     double gS0, gS1, gS2, lapS;
-    if constexpr (MF > 0) {
+    if constexpr (BF) {
+        // the backflow stage returns them directly (the Laplacian in full
+        // on electron 0's lane)
+        gS0 = c.bgS0;
+        gS1 = c.bgS1;
+        gS2 = c.bgS2;
+        lapS = c.blap;
+    } else if constexpr (MF > 0) {
         ao_weights_mfma<NMO, MF>(S, L.lane, stage, c.av);
         sigma_derivs_t<float>(S, x0, x1, x2, make_stage(stage).out + L.lane * kRowF, gS0, gS1, gS2, lapS);
     } else {
@@ -54,23 +61,24 @@ __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const La
     return res;
 }
 
-template <int NMO, bool EXPL>
+template <int NMO, bool EXPL, bool BF>
 __device__ __forceinline__ int lds_per_walker(const DevSystem &S) {
-    if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
+    if constexpr (BF) return walker_lds_bf<NMO>(S);
+    else if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
     else return walker_lds<NMO>(S);
 }
 
 // The matrix-core forms ask for two waves per SIMD: left alone the compiler
 // spends a few registers more than that allows and the kernel runs at one.
 // The vector-unit forms are faster with the registers they choose.
-template <int NMO, typename RT, int MF, bool EXPL>
+template <int NMO, typename RT, int MF, bool EXPL, bool BF>
 __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
                                                  double *__restrict__ LP, double *__restrict__ SG,
                                                  double *__restrict__ EL) {
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL>(S);
+    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL, BF>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -78,7 +86,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, c
         x1 = p[1];
         x2 = p[2];
     }
-    const WalkerResult r = eval_walker<NMO, RT, MF, EXPL>(S, L, wsm, x0, x1, x2, smem);
+    const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, smem);
     if (L.wvalid && L.lw == 0) {
         LP[w] = r.logpsi;
         SG[w] = r.sign;
@@ -86,7 +94,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, c
     }
 }
 
-template <int NMO, typename RT, int MF, bool EXPL>
+template <int NMO, typename RT, int MF, bool EXPL, bool BF>
 __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSystem S, double *__restrict__ X,
                                                       double *__restrict__ LP, double *__restrict__ SG,
                                                       double *__restrict__ EL, int64_t W, int n_steps,
@@ -95,7 +103,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSyste
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL>(S);
+    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL, BF>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSyste
         const uint64_t bits = ((((uint64_t)ca[0]) << 32) | (uint64_t)ca[1]) >> 11;
         const double u = (double)bits * (1.0 / 9007199254740992.0);
 
-        const WalkerResult r = eval_walker<NMO, RT, MF, EXPL>(S, L, wsm, y0, y1, y2, smem);
+        const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, y0, y1, y2, smem);
         const bool acc = isfinite(r.logpsi) && (u < exp(2.0 * (r.logpsi - lp)));
         if (acc) {
             x0 = y0;
@@ -201,18 +209,19 @@ static int nmo_bucket(int n_mo) {
 
 int padded_mo(int n_mo) { return nmo_bucket(n_mo); }
 
-template <int NMO, typename RT, int MF, bool EXPL = false>
+template <int NMO, typename RT, int MF, bool EXPL = false, bool BF = false>
 static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL,
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
                            uint32_t woff, double *ACC, hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
-    size_t lds = (size_t)S.WPW * (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S)) * sizeof(double);
+    const int per = BF ? walker_lds_bf<NMO>(S) : (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S));
+    size_t lds = (size_t)S.WPW * per * sizeof(double);
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
     if (mc)
-        hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL>), dim3((unsigned)blocks), dim3(kWave), lds, st,
+        hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st,
                            S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
     else
-        hipLaunchKernelGGL((k_eval<NMO, RT, MF, EXPL>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
+        hipLaunchKernelGGL((k_eval<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
                            (const double *)X, W, LP, SG, EL);
     return hipGetLastError();
 }
@@ -227,6 +236,29 @@ static hipError_t launch_explicit(bool mc, const DevSystem &S, double *X, double
 #undef QMC_CASE
     }
     return hipErrorInvalidValue;
+}
+
+static hipError_t launch_backflow(bool mc, const DevSystem &S, double *X, double *LP, double *SG,
+                                  double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
+                                  uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
+    switch (S.nmo_pad) {
+#define QMC_CASE(N) \
+    case N: return launch_t<N, double, 0, false, true>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
+#undef QMC_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t backflow_lds_bytes(const DevSystem &S) {
+    int per = 0;
+    switch (S.nmo_pad) {
+#define QMC_CASE(N) \
+    case N: per = walker_lds_bf<N>(S); break;
+        QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
+#undef QMC_CASE
+    }
+    return (size_t)S.WPW * per * sizeof(double);
 }
 
 size_t explicit_lds_bytes(const DevSystem &S) {
@@ -255,7 +287,7 @@ static hipError_t launch_rt(bool mc, const DevSystem &S, double *X, double *LP, 
 
 // form: 0 FP64, 1 mixed FP32 (VALU), 2 mixed BF16 on the matrix cores with
 // split operands, 3 mixed BF16 single products, 4 FP64 with explicit
-// determinants.
+// determinants, 5 FP64 with backflow (explicit configurations).
 hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, double *LP, double *SG,
                           double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
                           uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
@@ -265,6 +297,7 @@ hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, doub
         case 2: return launch_rt<float, 3>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 3: return launch_rt<float, 1>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 4: return launch_explicit(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        case 5: return launch_backflow(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
     }
     return hipErrorInvalidValue;
 }

@@ -609,6 +609,7 @@ struct Core {
     double Ssum, logD_up, logD_dn, sgn_up, sgn_dn;
     int sing_walker;                      // > 0: a reference matrix is exactly singular
     double av[NMO];                       // a_e[m] = d log Sigma / d phi_m(r_e)
+    double bgS0, bgS1, bgS2, blap;        // backflow: grad_e Sigma / Sigma, lap Sigma / Sigma share
 };
 
 // Jastrow and Coulomb terms, pass 1 (MO values), in-place Gauss-Jordan of
@@ -620,14 +621,25 @@ template <int NMO>
 __device__ __forceinline__ void explicit_dets(const DevSystem &S, const Lane &L, double *wsm,
                                               const double (&phi)[NMO], Core<NMO> &c);
 
-template <int NMO, typename RT, int MF = 0, bool EXPL = false>
+// Backflow: grad and Laplacian of Sigma of the backflow-transformed
+// determinants (eq. nabla_d), every configuration explicitly.  Every lane of
+// the block must call it.  sPos holds the walker's bare positions.
+template <int NMO>
+__device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L, double *wsm, const double *sPos,
+                                              double x0, double x1, double x2, Core<NMO> &c);
+
+template <int NMO>
+__host__ __device__ inline int bf_pos_offset(const DevSystem &S);
+
+template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
                                             double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
     const int tstride = nmax * NMO;          // doubles per spin table
     double *sT = wsm;                        // [2][nmax][NMO]
     double *sC = sT + 2 * tstride;           // [2][nmax][NMO] after the elimination
-    double *sPos = wsm + pos_offset<NMO>(S); // [LW][3] before it
+    // [LW][3] before the elimination (with backflow: after the backflow tables)
+    double *sPos = wsm + (BF ? bf_pos_offset<NMO>(S) : pos_offset<NMO>(S));
     double *sPiv = sPos + 3 * S.LW;          // [2][NMO] during it
     // e-e-n table before the elimination: per lane [n_atoms][een_n][2]
     // factor values (f1, f2) of its electron, then [n_atoms][4] geometry
@@ -754,6 +766,11 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     c.gJ2 = gJ2;
     c.lapJ = lapJ;
     c.vpot = vpot;
+
+    if constexpr (BF) {
+        backflow_dets<NMO>(S, L, wsm, sPos, x0, x1, x2, c);
+        return;
+    }
 
     // ---- pass 1: MO values of this electron ------------------------------
     double a[NMO];
@@ -1132,3 +1149,5 @@ __device__ __forceinline__ void explicit_dets(const DevSystem &S, const Lane &L,
 
 }  // namespace walker
 }  // namespace qmc
+
+#include "qmc_backflow.h"

@@ -44,6 +44,7 @@ class qmc_system_desc(C.Structure):
         ("n_mo", C.c_int32), ("mo_coef", _dp), ("n_det", C.c_int32), ("occ_up", _ip),
         ("occ_dn", _ip), ("ci", _dp), ("jas_a_par", C.c_double), ("jas_a_anti", C.c_double),
         ("jas_b", C.c_double), ("jas_en", _dp), ("jas_een_n", C.c_int32), ("jas_een", _dp),
+        ("bf_omega", C.c_double),
     ]
 
 
@@ -132,6 +133,7 @@ def make_desc(sysd: dict):
     if een is not None and len(een) > 0:
         d.jas_een_n = int(np.asarray(een).shape[0])
         d.jas_een = f64("jas_een")
+    d.bf_omega = float(sysd.get("bf_omega") or 0.0)
     return d, keep
 
 

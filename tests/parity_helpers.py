@@ -18,14 +18,16 @@ COND_MAX, KAPPA_S_MAX, E_MAX = 1e8, 1e3, 1e4
 
 def _conditioning(o, sysd, X):
     """Per walker: largest condition number of the two reference Slater
-    matrices, the cancellation factor of the CI sum, and |E_kin| (from the
+    matrices (orbitals at the backflow-transformed positions when the system
+    has backflow), the cancellation factor of the CI sum, and |E_kin| (from the
     oracle's MO values and plain numpy determinants)."""
     nu = sysd["n_up"]
     cond = np.ones(X.shape[0])
     kap = np.ones(X.shape[0])
     ekin = np.zeros(X.shape[0])
     for w, x in enumerate(X):
-        phi = o.mo(x)[:, 0, :]
+        # with backflow the matrices hold the orbitals at the transformed positions
+        phi = o.mo(o.backflow(x) if sysd.get("bf_omega") else x)[:, 0, :]
         up, dn = phi[:nu], phi[nu:]
         for M, occ in ((up, sysd["occ_up"][0]), (dn, sysd["occ_dn"][0])):
             if M.size:

@@ -127,3 +127,24 @@ def test_valid_many_body_terms_pass_validation():
         with pytest.raises(qmc.QmcError) as ei:
             qmc.System(d)
         assert ei.value.status == qmc.QMC_EDEVICE
+
+
+@pytest.mark.parametrize("omega", [float("nan"), float("inf")])
+def test_create_rejects_non_finite_backflow(omega):
+    d = dict(synth.make_system("LiH"))
+    d["bf_omega"] = omega
+    with pytest.raises(qmc.QmcError) as ei:
+        qmc.System(d)
+    assert ei.value.status == qmc.QMC_EINVAL
+
+
+def test_valid_backflow_passes_validation():
+    import torch
+    d = dict(synth.make_system("CO"))
+    d["bf_omega"] = -0.3
+    if torch.cuda.is_available():
+        qmc.System(d).close()
+    else:
+        with pytest.raises(qmc.QmcError) as ei:
+            qmc.System(d)
+        assert ei.value.status == qmc.QMC_EDEVICE

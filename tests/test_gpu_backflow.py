@@ -1,0 +1,157 @@
+"""Inverse backflow (Methods, backflow transformation; kernel omega / r_ij of
+the Results section) on the HIP path against the FP64 oracle through the C
+ABI, to the same bar as the other FP64 parity tests: evaluation parity on all
+four molecules (several waves and a ragged tail), with the many-body Jastrow,
+on SD(n, n) expansions up to 126 configurations per spin, CO at 65536 walkers
+on sampled walkers, Metropolis decisions step by step, omega -> 0 against the
+no-backflow kernels, and the forms that decline backflow.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_09743_amd import synth
+from parity_helpers import LOG_TOL, _compare, _one_step_margin
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _bf(sysd, omega):
+    d = dict(sysd)
+    d["bf_omega"] = omega
+    return d
+
+
+@pytest.mark.parametrize("name,omega,W", [("H2", 0.35, 1000), ("LiH", 0.35, 997), ("LiH", -0.2, 130),
+                                          ("Li2", 0.25, 601), ("CO", 0.25, 515), ("CO", -0.1, 67)])
+def test_backflow_eval_parity(torch_cuda, oracle_mod, name, omega, W):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.make_system(name), omega)
+    X = synth.init_walkers(sysd, W, 81)
+    print(f"backflow eval {name} omega={omega} W={W}", flush=True)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"{name} backflow")
+    s.close()
+
+
+def test_backflow_many_body(torch_cuda, oracle_mod):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.with_many_body_jastrow(synth.make_system("Li2"), synth.MBJ_SEED["Li2"]), 0.3)
+    X = synth.init_walkers(sysd, 203, 82)
+    print("backflow + many-body Li2 W=203", flush=True)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, "Li2 backflow + many-body")
+    s.close()
+
+
+@pytest.mark.parametrize("sd,W", [(2, 130), (6, 130), (10, 66)])
+def test_backflow_sd_expansion(torch_cuda, oracle_mod, sd, W):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.with_sd_expansion(synth.make_system("CO"), sd, 5), 0.2)
+    X = synth.init_walkers(sysd, W, 83)
+    print(f"backflow CO SD({sd}) W={W}", flush=True)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"CO SD({sd}) backflow")
+    s.close()
+
+
+def test_backflow_full_size_co_sampled(torch_cuda, oracle_mod):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.make_system("CO"), 0.25)
+    X = synth.init_walkers(sysd, 65536, synth.WALKER_SEED["CO"])
+    print("backflow CO W=65536", flush=True)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
+    idx = np.sort(np.random.default_rng(4).choice(65536, 128, replace=False))
+    idx[-1] = 65535
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X[idx], lp[idx], sg[idx], el[idx], "CO backflow 64k sampled")
+    s.close()
+
+
+@pytest.mark.parametrize("name,W,steps", [("LiH", 192, 8), ("CO", 64, 5)])
+def test_backflow_metropolis_stepwise(torch_cuda, oracle_mod, name, W, steps):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.make_system(name), 0.3)
+    o = oracle_mod.OracleSystem(sysd)
+    s = qmc.System(sysd)
+    seed, sigma = synth.PHILOX_SEED[name], 0.2
+    X = synth.init_walkers(sysd, W, 7)
+    lp, sg, el = o.eval(X)
+    print(f"backflow Metropolis {name} W={W} steps={steps}", flush=True)
+    flips = 0
+    for t in range(steps):
+        Xo, lpo, sgo, elo, _, log = o.metropolis(X, lp, sg, el, 1, sigma, seed, step0=t, want_log=True)
+        tX = torch.from_numpy(X.copy()).cuda()
+        tl, ts, te = (torch.from_numpy(v.copy()).cuda() for v in (lp, sg, el))
+        acc = s.metropolis(tX, tl, ts, te, 1, sigma, seed, step0=t)
+        torch.cuda.synchronize()
+        mism = acc.cpu().numpy()[:, 2] != log[0]
+        if mism.any():
+            margin = _one_step_margin(o, sysd, X, lp, seed, t, sigma, oracle_mod)
+            assert np.all(margin[mism] < 1e-9), f"step {t}: decision mismatch away from a tie"
+            flips += int(mism.sum())
+        same = ~mism
+        assert np.max(np.abs(tX.cpu().numpy()[same] - Xo[same])) < 1e-12
+        glp = tl.cpu().numpy()
+        assert np.max(np.abs(glp[same] - lpo[same]) / np.maximum(1, np.abs(lpo[same]))) < LOG_TOL
+        X, lp, sg, el = Xo, lpo, sgo, elo
+    assert flips == 0
+    s.close()
+
+
+def test_backflow_small_omega_equals_plain(torch_cuda):
+    """omega = 1e-300 runs the backflow kernel, whose results must equal the
+    low-rank kernel's without backflow to the parity tolerances."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    base = synth.make_system("CO")
+    X = torch.from_numpy(synth.init_walkers(base, 260, 9)).cuda()
+    a, b = qmc.System(base), qmc.System(_bf(base, 1e-300))
+    (l0, s0, e0), (l1, s1, e1) = [[t.cpu().numpy() for t in sys_.eval(X)] for sys_ in (a, b)]
+    ok = np.isfinite(l0)
+    assert np.array_equal(ok, np.isfinite(l1))
+    assert np.array_equal(s0[ok], s1[ok])
+    assert np.max(np.abs(l0[ok] - l1[ok]) / np.maximum(1, np.abs(l0[ok]))) < LOG_TOL
+    assert np.median(np.abs(e0[ok] - e1[ok])) < 1e-10
+    a.close()
+    b.close()
+
+
+def test_backflow_explicit_flag_same_kernel(torch_cuda):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.make_system("LiH"), 0.3)
+    X = torch.from_numpy(synth.init_walkers(sysd, 100, 2)).cuda()
+    s = qmc.System(sysd)
+    for u, v in zip(s.eval(X), s.eval(X, precision="fp64_explicit")):
+        assert torch.equal(torch.nan_to_num(u, nan=7.0), torch.nan_to_num(v, nan=7.0))
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x1"])
+def test_backflow_mixed_declined(torch_cuda, prec):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    s = qmc.System(_bf(synth.make_system("LiH"), 0.3))
+    X = torch.from_numpy(synth.init_walkers(s.sysd, 8, 1)).cuda()
+    with pytest.raises(qmc.QmcError) as e:
+        s.eval(X, precision=prec)
+    assert e.value.status == qmc.QMC_EUNSUPPORTED
+    with pytest.raises(qmc.QmcError) as e:
+        s.grad(X)
+    assert e.value.status == qmc.QMC_EUNSUPPORTED
+    s.close()
