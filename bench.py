@@ -79,6 +79,44 @@ def flops_per_walker_step(sysd) -> dict:
     return f
 
 
+def backflow_flops_per_walker_step(sysd) -> dict:
+    """Algorithmic FP operations of one walker-step with the inverse backflow
+    (same counting rules), every distinct spin configuration explicitly:
+    the map q, the Jacobian blocks and their products Y_ii' = sum_j J_ij
+    J_i'j, AO values, gradients and contracted Hessians at q with the MO
+    contraction of five channels, per configuration a Gauss-Jordan
+    inverse, the Mt rows, the three traces of eq. nabla_d and the
+    other spin's Y g, per determinant its weight and cross term, and the
+    gradient assembly sum_i J_ij g_i."""
+    from paper_2506_09743_amd import synth
+    ne, nu, nd = synth.n_elec(sysd), int(sysd["n_up"]), int(sysd["n_dn"])
+    na = len(sysd["Z"])
+    nmo = int(np.asarray(sysd["mo_coef"]).shape[1])
+    nao = synth.n_ao(sysd)
+    sto = sysd["basis"] == "sto"
+    n_prim = int(np.sum(sysd["shell_nprim"]))
+    n_sh = len(sysd["shell_l"])
+    ncfg = [len({tuple(r) for r in np.asarray(sysd[k]).reshape(len(sysd["ci"]), -1).tolist()})
+            for k in ("occ_up", "occ_dn")]
+    f = {}
+    f["proposal"] = ne * (6 + 3 * 2 + 7)
+    f["pairs"] = (ne * (ne - 1) // 2) * 25 + ne * na * 9
+    f["bf_map"] = ne * (ne - 1) * 35
+    f["jacobian_products"] = ne * ne * 12 + ne ** 3 * 54
+    f["ao"] = ne * (n_sh * 20 + n_prim * ((17 if sto else 13) + 6) + nao * 40)
+    f["mo"] = ne * 2 * 5 * nao * nmo
+    cf = 0
+    for n, no, nc in ((nu, nd, ncfg[0]), (nd, nu, ncfg[1])):
+        cf += nc * (2 * n ** 3 + 6 * n ** 3 + 2 * n * n + 48 * n * n + 24 * n * no)
+    f["configurations"] = cf
+    f["determinants"] = len(sysd["ci"]) * (4 + 6 * max(nu, nd))
+    f["gradient"] = ne * ne * 30
+    f["eloc"] = ne * 15 + 10
+    f["accept"] = 6
+    f["total"] = sum(f.values())
+    return f
+
+
 def grad_flops_per_walker(sysd) -> dict:
     """Algorithmic FP operations of one walker's qmc_grad (estimate from the
     shapes): the forward Psi / E_L evaluation, the forward-mode determinant
@@ -317,6 +355,94 @@ def sd_sweep_bench(args, dev) -> list:
     return rows
 
 
+BF_OMEGA = 0.1
+
+
+def backflow_bench(args, dev, seed) -> dict:
+    """The inverse backflow (omega / r_ij, omega = 0.1) on CO, FP64, every
+    configuration explicitly: Metropolis throughput at the full walker
+    count with its roofline, errors against the oracle on sampled walkers,
+    and the E_L evaluation time of the SD(n, n) expansions at 1000 walkers
+    with and without backflow."""
+    import torch
+    import oracle
+    from paper_2506_09743_amd import qmc, synth
+    base = synth.make_system("CO")
+    sysd = dict(base)
+    sysd["bf_omega"] = BF_OMEGA
+    W = args.walkers
+    system = qmc.System(sysd, device=0)
+    X = torch.from_numpy(synth.init_walkers(sysd, W, synth.WALKER_SEED["CO"])).to(dev)
+    lp, sg, el = system.eval(X)
+    acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+    step = 0
+    for _ in range(2):  # burn-in and warm-up
+        system.metropolis(X, lp, sg, el, args.chunk, 0.2, seed, step0=step, acc=acc)
+        step += args.chunk
+    acc.zero_()
+    events = []
+    n_launch = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_launch):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        system.metropolis(X, lp, sg, el, args.chunk, 0.2, seed, step0=step, acc=acc)
+        e1.record()
+        events.append((e0, e1))
+        step += args.chunk
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    fl = backflow_flops_per_walker_step(sysd)
+    achieved = fl["total"] * W * args.chunk / (launch_ms * 1e-3)
+    idx = np.random.default_rng(0).choice(W, size=min(128, W), replace=False)
+    Xn = X.cpu().numpy()[idx]
+    rlp, _, rel = oracle.OracleSystem(sysd).eval(Xn)
+    glp, _, gel = [t.cpu().numpy()[idx] for t in system.eval(X)]
+    ok = np.isfinite(rel) & np.isfinite(gel)
+    system.close()
+
+    def timed(fn, reps=3):
+        fn()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    sweep = []
+    for n in (2, 4, 6, 8, 10):
+        sd = synth.with_sd_expansion(base, n, 5)
+        sdb = dict(sd)
+        sdb["bf_omega"] = BF_OMEGA
+        a, b = qmc.System(sd, device=0), qmc.System(sdb, device=0)
+        Xs = torch.from_numpy(synth.init_walkers(sd, 1000, synth.WALKER_SEED["CO"])).to(dev)
+        outs = [torch.empty(1000, dtype=torch.float64, device=dev) for _ in range(3)]
+        t_lr = timed(lambda: qmc.qmc_eval_psi_eloc(a.handle, qmc.QMC_FP64, Xs, *outs))
+        t_ex = timed(lambda: qmc.qmc_eval_psi_eloc(a.handle, qmc.QMC_FP64_EXPLICIT, Xs, *outs))
+        t_bf = timed(lambda: qmc.qmc_eval_psi_eloc(b.handle, qmc.QMC_FP64, Xs, *outs))
+        sweep.append({"sd": f"SD({n},{n})", "dets": len(sd["ci"]), "eval_ms_low_rank": t_lr,
+                      "eval_ms_explicit": t_ex, "eval_ms_backflow_explicit": t_bf,
+                      "backflow_over_explicit": t_bf / t_ex})
+        a.close()
+        b.close()
+    return {"workload": f"CO, 100 determinants, {W} walkers, inverse backflow omega = {BF_OMEGA}",
+            "value": W * args.chunk * n_launch / dt, "unit": "walker-steps/s", "dtype": "f64",
+            "launch_ms_mean": launch_ms, "launch_steps": args.chunk,
+            "flops_per_walker_step": fl["total"],
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU},
+            "median_abs_dE_L": float(np.median(np.abs(gel[ok] - rel[ok]))),
+            "max_abs_dE_L": float(np.max(np.abs(gel[ok] - rel[ok]))),
+            "max_rel_dlogpsi": float(np.max(np.abs(glp[ok] - rlp[ok]) / np.maximum(1, np.abs(rlp[ok])))),
+            "sd_sweep_1000_walkers": sweep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +459,7 @@ def main():
     ap.add_argument("--no-sd-sweep", action="store_true",
                     help="skip the determinant-count sweep (low-rank vs explicit)")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (qmc_grad) measurement")
+    ap.add_argument("--no-backflow", action="store_true", help="skip the inverse backflow measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests in the serving measurement (0: skip)")
@@ -433,6 +560,7 @@ def main():
     if not args.no_sd_sweep and args.system == "CO":
         sd_sweep = sd_sweep_bench(args, dev)
     gradient = None if args.no_grad else grad_bench(args, dev)
+    backflow = None if args.no_backflow else backflow_bench(args, dev, seed)
 
     fl = flops_per_walker_step(sysd)
     main_form = results["fp64"]
@@ -480,6 +608,7 @@ def main():
         "many_body_jastrow": many_body,
         "determinant_sweep": sd_sweep,
         "gradient": gradient,
+        "backflow": backflow,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -95,8 +95,8 @@ def test_mbj_metropolis_stepwise_parity(torch_cuda, oracle_mod, name, W, steps):
 
 @pytest.mark.parametrize("prec,med_tol", [("fp32", 1e-4), ("bf16", 2e-3)])
 def test_mbj_mixed_error(torch_cuda, oracle_mod, prec, med_tol):
-    """The Jastrow stays FP64 in the mixed forms: their error is the orbital
-    error alone, as without the many-body terms."""
+    """The many-body Jastrow terms stay FP64 in the mixed forms, so their
+    error is that of the Pade-only system's mixed evaluation."""
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
     sysd = _mbj("CO")
