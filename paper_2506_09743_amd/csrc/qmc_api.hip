@@ -25,7 +25,7 @@ hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *d
                        hipStream_t st);
 size_t grad_lds_bytes(const DevSystem &S);
 size_t explicit_lds_bytes(const DevSystem &S);
-size_t backflow_lds_bytes(const DevSystem &S);
+size_t backflow_lds_bytes(const DevSystem &S, bool low_rank);
 }  // namespace qmc
 
 using qmc::DevSystem;
@@ -345,6 +345,19 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     }
     const int n_cfg_max = (int)std::max(cfgs[0].size(), cfgs[1].size());
     std::vector<int> cfg_occ(2 * n_cfg_max * qmc::kMaxSpin, 0);
+    // canonical excitation of every configuration (low-rank backflow)
+    std::vector<int> cfg_exc(2 * n_cfg_max, 0);
+    for (int s = 0; s < 2; ++s)
+        for (size_t q = 0; q < cfgs[s].size(); ++q) {
+            Excitation ex;
+            double sg = 1.0;
+            const int r = canonical_excitation(cfgs[s][q], (int)cfgs[s][q].size(), &ex, &sg);
+            if (r < 0) return QMC_EUNSUPPORTED;
+            int code = 1 << 21;  // repeated MO: identically zero
+            if (r > 0)
+                code = ex.rank | ex.h[0] << 2 | ex.h[1] << 5 | ex.p[0] << 8 | ex.p[1] << 13 | (sg < 0.0 ? 1 << 20 : 0);
+            cfg_exc[s * n_cfg_max + q] = code;
+        }
     for (int s = 0; s < 2; ++s)
         for (size_t q = 0; q < cfgs[s].size(); ++q)
             for (size_t k = 0; k < cfgs[s][q].size(); ++k) cfg_occ[(s * n_cfg_max + q) * qmc::kMaxSpin + k] = cfgs[s][q][k];
@@ -508,6 +521,7 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     const size_t o_cix = push_bytes(blob, ci_x.data(), ci_x.size());
     const size_t o_coff = push_bytes(blob, cfg_off.data(), cfg_off.size());
     const size_t o_cuse = push_bytes(blob, cfg_use.data(), cfg_use.size());
+    const size_t o_cexc = push_bytes(blob, cfg_exc.data(), cfg_exc.size());
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return QMC_EDEVICE;
@@ -576,6 +590,7 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.cfg_off = (const int *)(base + o_coff);
     S.cfg_use = (const int2 *)(base + o_cuse);
     S.bf_omega = d->bf_omega;
+    S.cfg_exc = (const int *)(base + o_cexc);
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
@@ -600,9 +615,11 @@ static qmc_status check_walk_args(qmc_system *sys, int32_t precision, int64_t W)
     if ((precision == QMC_MIXED_BF16 || precision == QMC_MIXED_BF16_X1) && sys->S.n_ao > 32)
         return QMC_EUNSUPPORTED;
     if (sys->S.bf_omega != 0.0) {
-        // backflow: FP64 only, explicit configurations
+        // backflow: FP64 only; QMC_FP64 updates the configurations from the
+        // reference, QMC_FP64_EXPLICIT factorises each
         if (precision != QMC_FP64 && precision != QMC_FP64_EXPLICIT) return QMC_EUNSUPPORTED;
-        if (sys->S.n_cfg_max > qmc::kMaxCfgBF || qmc::backflow_lds_bytes(sys->S) > 160 * 1024)
+        if (sys->S.n_cfg_max > qmc::kMaxCfgBF ||
+            qmc::backflow_lds_bytes(sys->S, precision == QMC_FP64) > 160 * 1024)
             return QMC_EUNSUPPORTED;
         return QMC_OK;
     }
@@ -610,9 +627,11 @@ static qmc_status check_walk_args(qmc_system *sys, int32_t precision, int64_t W)
     return QMC_OK;
 }
 
-// Kernel form of a call: the precision, or 5 for the backflow evaluation.
+// Kernel form of a call: the precision, or with backflow 6 (low-rank) / 5
+// (every configuration factorised).
 static int walk_form(const qmc_system *sys, int32_t precision) {
-    return sys->S.bf_omega != 0.0 ? 5 : precision;
+    if (sys->S.bf_omega == 0.0) return precision;
+    return precision == QMC_FP64_EXPLICIT ? 5 : 6;
 }
 
 qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d_X, int64_t W,

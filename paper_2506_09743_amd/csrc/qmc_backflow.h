@@ -45,25 +45,82 @@ __device__ __forceinline__ int lane_of(const DevSystem &S, int j) {
     return j < S.n_up ? j : S.G + (j - S.n_up);
 }
 
-// LDS of one walker with backflow (doubles), from the walker's base:
-// diagonal Jacobian blocks [LW][6], inverse tables [2][G][8], pivot rows
-// [2][8], Mt rows [2][G][3][8], published g [2][G][3], per configuration
-// (log|D|, sign, weight, L, scaled value) [2][n_cfg_max][5], weighted
-// g [LW][3]; the positions follow at bf_pos_offset.
-__host__ __device__ inline int bf_table_size(const DevSystem &S) {
-    return 6 * S.LW + 2 * S.G * kMaxSpin + 2 * kMaxSpin + 2 * S.G * 3 * kMaxSpin + 2 * S.G * 3 +
-           10 * S.n_cfg_max + 3 * S.LW;
+// LDS of one walker with backflow (doubles), from the walker's base.  A
+// shared region holds in turn the diagonal Jacobian blocks [LW][6] (while
+// the Y rows are built), the determinant tables of the configuration loop
+// (low-rank: the reference rows [2][nmax][NMO] = A0^-1 | T and pivot rows
+// [2][NMO]; explicit: inverse tables [2][G][8] and pivot rows [2][8]) and
+// the weighted g [LW][3] (at the end).  Then Mt rows [2][G][3][8], published
+// g [2][G][3] and per configuration (log|D|, sign, weight, L, scaled value)
+// [2][n_cfg_max][5]; the positions follow at bf_pos_offset.
+template <int NMO, bool LR>
+__host__ __device__ inline int bf_shared_size(const DevSystem &S) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int dets = LR ? 2 * nmax * NMO + 2 * NMO : 2 * S.G * kMaxSpin + 2 * kMaxSpin;
+    const int a = 6 * S.LW > dets ? 6 * S.LW : dets;
+    return a > 3 * S.LW ? a : 3 * S.LW;
 }
 
-template <int NMO>
+template <int NMO, bool LR>
+__host__ __device__ inline int bf_table_size(const DevSystem &S) {
+    return bf_shared_size<NMO, LR>(S) + 2 * S.G * 3 * kMaxSpin + 2 * S.G * 3 + 10 * S.n_cfg_max;
+}
+
+template <int NMO, bool LR>
 __host__ __device__ inline int bf_pos_offset(const DevSystem &S) {
-    const int a = pos_offset<NMO>(S), b = bf_table_size(S);
+    const int a = pos_offset<NMO>(S), b = bf_table_size<NMO, LR>(S);
     return a > b ? a : b;
 }
 
-template <int NMO>
+template <int NMO, bool LR>
 __host__ __device__ inline int walker_lds_bf(const DevSystem &S) {
-    return bf_pos_offset<NMO>(S) + 3 * S.LW;
+    return bf_pos_offset<NMO, LR>(S) + 3 * S.LW;
+}
+
+// In-place Gauss-Jordan of the spin group's reference rows [A0 | Phi]
+// (NMO entries per lane, reference orbitals in columns 0..n-1): afterwards
+// the row of slot s holds A0^-1[s][slot(e)] in the columns < n and
+// T[s][v] = (A0^-1 Phi)[s][v] in the others.  Every lane of the block runs
+// the same steps (block barriers inside).
+template <int NMO>
+__device__ __forceinline__ void reference_gauss_jordan(const DevSystem &S, const Lane &L, double (&a)[NMO], int nmax,
+                                                       double *piv_row, int &slot, double &dprod, bool &singular) {
+    constexpr int JMAX = kMaxSpin < NMO ? kMaxSpin : NMO;
+    bool done = !L.active;
+    slot = -1;
+    dprod = 1.0;
+    singular = false;
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        if (j >= nmax) break;
+        const bool work = j < L.nsig;
+        double cand = (work && !done) ? fabs(a[j]) : -1.0;
+        int cl = L.i;
+        span_argmax(cand, cl, S.G);
+        const bool ok = work && cand > 0.0;
+        if (work && !ok) singular = true;
+        const bool is_piv = ok && L.active && L.i == cl;
+        if (is_piv) {
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) piv_row[m] = a[m];
+            const double inv = 1.0 / a[j];
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) a[m] *= inv;
+            a[j] = inv;
+            done = true;
+            slot = j;
+        }
+        __syncthreads();
+        const double piv = ok ? piv_row[j] : 0.0;
+        if (work) dprod *= piv;
+        if (ok && L.active && !is_piv) {
+            const double f = a[j] / piv;
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) a[m] -= f * piv_row[m];
+            a[j] = -f;
+        }
+        __syncthreads();
+    }
 }
 
 // Symmetric 3 x 3 block (xx, xy, xz, yy, yz, zz) of J_ij for i != j from the
@@ -188,19 +245,24 @@ __device__ __forceinline__ void mo_component_bf(const DevSystem &S, int comp, do
     }
 }
 
-template <int NMO>
+// LR: configurations from the reference by the rank <= 2 update of
+// eq. table (only A0 is factorised); otherwise every configuration is
+// factorised on its own.
+template <int NMO, bool LR>
 __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L, double *wsm, const double *sPos,
                                               double x0, double x1, double x2, Core<NMO> &c) {
     const int LW = S.LW, nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
     const double om = S.bf_omega;
     const int G = S.G;
-    double *sJd = wsm;                                      // [LW][6]
-    double *sInv = sJd + 6 * LW;                            // [2][G][8]
+    double *sJd = wsm;                                      // [LW][6] (shared region)
+    double *sInv = wsm;                                     // [2][G][8] (shared region, explicit)
     double *sPv = sInv + 2 * G * kMaxSpin;                  // [2][8]
-    double *sMt = sPv + 2 * kMaxSpin;                       // [2][G][3][8]
+    double *sRef = wsm;                                     // [2][nmax][NMO] (shared region, low-rank)
+    double *sPvN = sRef + 2 * nmax * NMO;                   // [2][NMO]
+    double *sGb = wsm;                                      // [LW][3] (shared region, at the end)
+    double *sMt = wsm + bf_shared_size<NMO, LR>(S);         // [2][G][3][8]
     double *sGp = sMt + 2 * G * 3 * kMaxSpin;               // [2][G][3]
     double *sCfg = sGp + 2 * G * 3;                         // [2][n_cfg_max][5]
-    double *sGb = sCfg + 10 * S.n_cfg_max;                  // [LW][3]
     double *inv_g = sInv + L.grp * G * kMaxSpin;
     double *piv_g = sPv + L.grp * kMaxSpin;
     double *mt_g = sMt + L.grp * 3 * G * kMaxSpin;
@@ -315,53 +377,178 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         }
     }
 
+    __syncthreads();  // every lane has read the shared region's J blocks
+
+    // ---- low-rank: the reference once --------------------------------------
+    // Reference rows [A0 | Phi] by Gauss-Jordan; then per lane the reference
+    // Mt row Mt0[b][i'] = sum_k d_b phi_k(q_i) A0^-1[k][i'], the first trace
+    // t10 = sum_k A0^-1[k][i] psi_k(i), and the residual rows
+    // Z[b][m] = d_b phi_m(q_i) - sum_k d_b phi_k(q_i) T[k][m] (b = 3: psi),
+    // which vanish on the reference columns.  A configuration with holes H
+    // and particles P (canonical order, sign s_c) then has
+    // det A_c = s_c D0 det R, R = T[H, P], and
+    // Mt_c = Mt0 + Z[:, P] R^-1 A0^-1[H, :], t1_c = t10 + sum_i Zpsi[i, P] R^-1 A0^-1[H, i].
+    double Mt0[3][kMaxSpin];
+    double t10 = 0.0, ref_log = 0.0, ref_sgn = 1.0;
+    bool ref_sing = false;
+    double zt[LR ? 4 * NMO : 1];
+    int rslots[kMaxSpin];
+    double *ref_g = sRef + L.grp * nmax * NMO;
+    if constexpr (LR) {
+        double a[NMO];
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) a[m] = L.active ? tab[m] : 0.0;
+        int slot;
+        double dprod;
+        reference_gauss_jordan<NMO>(S, L, a, nmax, sPvN + L.grp * NMO, slot, dprod, ref_sing);
+        ref_sgn = group_parity(S, L, slot) * (dprod < 0.0 ? -1.0 : 1.0);
+        ref_log = log(fabs(dprod));
+        if (L.active && slot >= 0) {
+#pragma unroll
+            for (int m = 0; m < NMO; ++m) ref_g[slot * NMO + m] = a[m];
+        }
+#pragma unroll
+        for (int ip = 0; ip < kMaxSpin; ++ip) rslots[ip] = ip < S.G ? __shfl(slot, L.gbase + ip) : -1;
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int ip = 0; ip < kMaxSpin; ++ip) Mt0[b][ip] = 0.0;
+        if (L.active && !ref_sing) {
+#pragma unroll
+            for (int k = 0; k < kMaxSpin; ++k) {
+                if (k >= L.nsig) break;
+                const double gx = tab[2 * NMO + k], gy = tab[3 * NMO + k], gz = tab[4 * NMO + k];
+                const double *irow = ref_g + k * NMO;
+#pragma unroll
+                for (int ip = 0; ip < kMaxSpin; ++ip) {
+                    if (ip >= L.nsig) break;
+                    const double v = irow[rslots[ip]];
+                    Mt0[0][ip] += gx * v;
+                    Mt0[1][ip] += gy * v;
+                    Mt0[2][ip] += gz * v;
+                }
+                t10 += irow[slot] * tab[NMO + k];
+            }
+            for (int m = 0; m < NMO; ++m) {
+                double z0 = tab[2 * NMO + m], z1 = tab[3 * NMO + m], z2 = tab[4 * NMO + m], z3 = tab[NMO + m];
+                if (m >= L.nsig) {
+                    for (int k = 0; k < L.nsig; ++k) {
+                        const double t = ref_g[k * NMO + m];
+                        z0 -= tab[2 * NMO + k] * t;
+                        z1 -= tab[3 * NMO + k] * t;
+                        z2 -= tab[4 * NMO + k] * t;
+                        z3 -= tab[NMO + k] * t;
+                    }
+                } else {
+                    z0 = z1 = z2 = z3 = 0.0;
+                }
+                zt[m] = z0;
+                zt[NMO + m] = z1;
+                zt[2 * NMO + m] = z2;
+                zt[3 * NMO + m] = z3;
+            }
+        }
+    }
+
     // ---- every configuration of each spin --------------------------------
     double gtab[kMaxCfgBF * 3], vtab[kMaxCfgBF * 3];
     for (int q = 0; q < ncmax; ++q) {
         const bool live = q < ncfg_g;
-        const int *occ = occ_g + (live ? q : 0) * kMaxSpin;
-        double a[kMaxSpin];
-#pragma unroll
-        for (int k = 0; k < kMaxSpin; ++k)
-            a[k] = (L.active && live && k < L.nsig) ? tab[occ[k]] : 0.0;
-        int slot;
-        double dprod;
-        bool singular;
-        group_gauss_jordan(S, L, a, L.nsig, nmax, live, piv_g, slot, dprod, singular);
-        const double par = group_parity(S, L, slot);
-        if (live && L.active && slot >= 0) {
-#pragma unroll
-            for (int k = 0; k < kMaxSpin; ++k) inv_g[slot * kMaxSpin + k] = a[k];
-        }
-        int slots[kMaxSpin];
-#pragma unroll
-        for (int ip = 0; ip < kMaxSpin; ++ip) slots[ip] = ip < S.G ? __shfl(slot, L.gbase + ip) : -1;
-        __syncthreads();
-
-        // Mt row, g_i and the first trace; A^-1[k][i'] = inv[k][slot(i')]
-        const bool ok = live && L.active && !singular;
         double Mt[3][kMaxSpin];
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int ip = 0; ip < kMaxSpin; ++ip) Mt[b][ip] = 0.0;
-        double t1 = 0.0;
-        if (ok) {
-#pragma unroll
-            for (int k = 0; k < kMaxSpin; ++k) {
-                if (k >= L.nsig) break;
-                const int mo = occ[k];
-                const double gx = tab[2 * NMO + mo], gy = tab[3 * NMO + mo], gz = tab[4 * NMO + mo];
-                const double *irow = inv_g + k * kMaxSpin;
+        double t1 = 0.0, clog = -INFINITY, csgn = 0.0;
+        bool singular, ok;
+        if constexpr (LR) {
+            // code: rank | h0 << 2 | h1 << 5 | p0 << 8 | p1 << 13, bit 20: odd
+            // permutation to canonical order, bit 21: identically zero
+            const int code = live ? S.cfg_exc[L.grp * S.n_cfg_max + q] : 0;
+            const int rk = code & 3, h0 = (code >> 2) & 7, h1 = (code >> 5) & 7;
+            const int p0 = (code >> 8) & 31, p1 = (code >> 13) & 31;
+            double R00 = 1.0, R01 = 0.0, R10 = 0.0, R11 = 1.0;
+            if (rk >= 1) R00 = ref_g[h0 * NMO + p0];
+            if (rk == 2) {
+                R01 = ref_g[h0 * NMO + p1];
+                R10 = ref_g[h1 * NMO + p0];
+                R11 = ref_g[h1 * NMO + p1];
+            }
+            const double detR = rk == 2 ? R00 * R11 - R01 * R10 : R00;
+            singular = !live || ref_sing || ((code >> 21) & 1) || detR == 0.0;
+            ok = !singular && L.active;
+            if (!singular) {
+                clog = ref_log + log(fabs(detR));
+                csgn = ref_sgn * (((code >> 20) & 1) ? -1.0 : 1.0) * (detR < 0.0 ? -1.0 : 1.0);
+            }
+            if (ok) {
+                // R^-1 (rows particles, columns holes)
+                const double di = 1.0 / detR;
+                const double Q00 = rk == 2 ? R11 * di : di, Q01 = -R01 * di, Q10 = -R10 * di, Q11 = R00 * di;
+                const double za0 = zt[p0], za1 = zt[NMO + p0], za2 = zt[2 * NMO + p0], zap = zt[3 * NMO + p0];
+                const double zb0 = rk == 2 ? zt[p1] : 0.0, zb1 = rk == 2 ? zt[NMO + p1] : 0.0;
+                const double zb2 = rk == 2 ? zt[2 * NMO + p1] : 0.0, zbp = rk == 2 ? zt[3 * NMO + p1] : 0.0;
+                const double *hr0 = ref_g + h0 * NMO, *hr1 = ref_g + h1 * NMO;
 #pragma unroll
                 for (int ip = 0; ip < kMaxSpin; ++ip) {
                     if (ip >= L.nsig) break;
-                    const double v = irow[slots[ip]];
-                    Mt[0][ip] += gx * v;
-                    Mt[1][ip] += gy * v;
-                    Mt[2][ip] += gz * v;
+                    double d0 = 0.0, d1 = 0.0;  // (R^-1 A0^-1[H, i'])_j
+                    if (rk == 1) {
+                        d0 = Q00 * hr0[rslots[ip]];
+                    } else if (rk == 2) {
+                        const double v0 = hr0[rslots[ip]], v1 = hr1[rslots[ip]];
+                        d0 = Q00 * v0 + Q01 * v1;
+                        d1 = Q10 * v0 + Q11 * v1;
+                    }
+                    Mt[0][ip] = Mt0[0][ip] + za0 * d0 + zb0 * d1;
+                    Mt[1][ip] = Mt0[1][ip] + za1 * d0 + zb1 * d1;
+                    Mt[2][ip] = Mt0[2][ip] + za2 * d0 + zb2 * d1;
+                    if (ip == L.i) t1 = t10 + zap * d0 + zbp * d1;
                 }
-                t1 += irow[slot] * tab[NMO + mo];
+            }
+        } else {
+            const int *occ = occ_g + (live ? q : 0) * kMaxSpin;
+            double a[kMaxSpin];
+#pragma unroll
+            for (int k = 0; k < kMaxSpin; ++k)
+                a[k] = (L.active && live && k < L.nsig) ? tab[occ[k]] : 0.0;
+            int slot;
+            double dprod;
+            group_gauss_jordan(S, L, a, L.nsig, nmax, live, piv_g, slot, dprod, singular);
+            const double par = group_parity(S, L, slot);
+            if (live && !singular) {
+                clog = log(fabs(dprod));
+                csgn = par * (dprod < 0.0 ? -1.0 : 1.0);
+            }
+            if (live && L.active && slot >= 0) {
+#pragma unroll
+                for (int k = 0; k < kMaxSpin; ++k) inv_g[slot * kMaxSpin + k] = a[k];
+            }
+            int slots[kMaxSpin];
+#pragma unroll
+            for (int ip = 0; ip < kMaxSpin; ++ip) slots[ip] = ip < S.G ? __shfl(slot, L.gbase + ip) : -1;
+            __syncthreads();
+
+            // Mt row, g_i and the first trace; A^-1[k][i'] = inv[k][slot(i')]
+            ok = live && L.active && !singular;
+            if (ok) {
+#pragma unroll
+                for (int k = 0; k < kMaxSpin; ++k) {
+                    if (k >= L.nsig) break;
+                    const int mo = occ[k];
+                    const double gx = tab[2 * NMO + mo], gy = tab[3 * NMO + mo], gz = tab[4 * NMO + mo];
+                    const double *irow = inv_g + k * kMaxSpin;
+#pragma unroll
+                    for (int ip = 0; ip < kMaxSpin; ++ip) {
+                        if (ip >= L.nsig) break;
+                        const double v = irow[slots[ip]];
+                        Mt[0][ip] += gx * v;
+                        Mt[1][ip] += gy * v;
+                        Mt[2][ip] += gz * v;
+                    }
+                    t1 += irow[slot] * tab[NMO + mo];
+                }
             }
         }
         double g0 = 0.0, g1 = 0.0, g2 = 0.0;
@@ -431,8 +618,8 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         }
         const double Lc = span_sum(ok ? t1 + gg - t3 : 0.0, S.G);
         if (live && L.i == 0) {
-            cfg_g[5 * q] = singular ? -INFINITY : log(fabs(dprod));
-            cfg_g[5 * q + 1] = singular ? 0.0 : par * (dprod < 0.0 ? -1.0 : 1.0);
+            cfg_g[5 * q] = singular ? -INFINITY : clog;
+            cfg_g[5 * q + 1] = singular ? 0.0 : csgn;
             cfg_g[5 * q + 3] = singular ? 0.0 : Lc;
         }
         __syncthreads();

@@ -68,6 +68,11 @@ struct DevSystem {
     const int2 *cfg_use;
     // Inverse backflow kernel omega / r_ij (0: none).
     double bf_omega;
+    // Per distinct spin configuration [2][n_cfg_max], its excitation from the
+    // reference in canonical order: rank | h0 << 2 | h1 << 5 | p0 << 8 |
+    // p1 << 13, bit 20 set when the configuration's column order is an odd
+    // permutation of the canonical one, bit 21 when a MO repeats (zero).
+    const int *cfg_exc;
 };
 
 // Largest number of e-e-n terms.

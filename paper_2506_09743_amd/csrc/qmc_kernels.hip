@@ -63,7 +63,7 @@ __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const La
 
 template <int NMO, bool EXPL, bool BF>
 __device__ __forceinline__ int lds_per_walker(const DevSystem &S) {
-    if constexpr (BF) return walker_lds_bf<NMO>(S);
+    if constexpr (BF) return walker_lds_bf<NMO, !EXPL>(S);
     else if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
     else return walker_lds<NMO>(S);
 }
@@ -214,7 +214,7 @@ static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, d
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
                            uint32_t woff, double *ACC, hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
-    const int per = BF ? walker_lds_bf<NMO>(S) : (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S));
+    const int per = BF ? walker_lds_bf<NMO, !EXPL>(S) : (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S));
     size_t lds = (size_t)S.WPW * per * sizeof(double);
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
     if (mc)
@@ -238,23 +238,26 @@ static hipError_t launch_explicit(bool mc, const DevSystem &S, double *X, double
     return hipErrorInvalidValue;
 }
 
+// Backflow: low-rank configurations (EXPL = false) or every configuration
+// factorised (EXPL = true).
+template <bool EXPL>
 static hipError_t launch_backflow(bool mc, const DevSystem &S, double *X, double *LP, double *SG,
                                   double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
                                   uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
     switch (S.nmo_pad) {
 #define QMC_CASE(N) \
-    case N: return launch_t<N, double, 0, false, true>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+    case N: return launch_t<N, double, 0, EXPL, true>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
 #undef QMC_CASE
     }
     return hipErrorInvalidValue;
 }
 
-size_t backflow_lds_bytes(const DevSystem &S) {
+size_t backflow_lds_bytes(const DevSystem &S, bool low_rank) {
     int per = 0;
     switch (S.nmo_pad) {
 #define QMC_CASE(N) \
-    case N: per = walker_lds_bf<N>(S); break;
+    case N: per = low_rank ? walker_lds_bf<N, true>(S) : walker_lds_bf<N, false>(S); break;
         QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
 #undef QMC_CASE
     }
@@ -287,7 +290,8 @@ static hipError_t launch_rt(bool mc, const DevSystem &S, double *X, double *LP, 
 
 // form: 0 FP64, 1 mixed FP32 (VALU), 2 mixed BF16 on the matrix cores with
 // split operands, 3 mixed BF16 single products, 4 FP64 with explicit
-// determinants, 5 FP64 with backflow (explicit configurations).
+// determinants, 5 FP64 with backflow and every configuration factorised,
+// 6 FP64 with backflow and the low-rank configuration update.
 hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, double *LP, double *SG,
                           double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
                           uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
@@ -297,7 +301,8 @@ hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, doub
         case 2: return launch_rt<float, 3>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 3: return launch_rt<float, 1>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 4: return launch_explicit(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
-        case 5: return launch_backflow(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        case 5: return launch_backflow<true>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
+        case 6: return launch_backflow<false>(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
     }
     return hipErrorInvalidValue;
 }

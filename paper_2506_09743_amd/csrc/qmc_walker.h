@@ -624,11 +624,11 @@ __device__ __forceinline__ void explicit_dets(const DevSystem &S, const Lane &L,
 // Backflow: grad and Laplacian of Sigma of the backflow-transformed
 // determinants (eq. nabla_d), every configuration explicitly.  Every lane of
 // the block must call it.  sPos holds the walker's bare positions.
-template <int NMO>
+template <int NMO, bool LR>
 __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L, double *wsm, const double *sPos,
                                               double x0, double x1, double x2, Core<NMO> &c);
 
-template <int NMO>
+template <int NMO, bool LR>
 __host__ __device__ inline int bf_pos_offset(const DevSystem &S);
 
 template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false>
@@ -639,7 +639,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     double *sT = wsm;                        // [2][nmax][NMO]
     double *sC = sT + 2 * tstride;           // [2][nmax][NMO] after the elimination
     // [LW][3] before the elimination (with backflow: after the backflow tables)
-    double *sPos = wsm + (BF ? bf_pos_offset<NMO>(S) : pos_offset<NMO>(S));
+    double *sPos = wsm + (BF ? bf_pos_offset<NMO, !EXPL>(S) : pos_offset<NMO>(S));
     double *sPiv = sPos + 3 * S.LW;          // [2][NMO] during it
     // e-e-n table before the elimination: per lane [n_atoms][een_n][2]
     // factor values (f1, f2) of its electron, then [n_atoms][4] geometry
@@ -768,7 +768,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     c.vpot = vpot;
 
     if constexpr (BF) {
-        backflow_dets<NMO>(S, L, wsm, sPos, x0, x1, x2, c);
+        backflow_dets<NMO, !EXPL>(S, L, wsm, sPos, x0, x1, x2, c);
         return;
     }
 

@@ -1,10 +1,13 @@
 """Inverse backflow (Methods, backflow transformation; kernel omega / r_ij of
 the Results section) on the HIP path against the FP64 oracle through the C
-ABI, to the same bar as the other FP64 parity tests: evaluation parity on all
-four molecules (several waves and a ragged tail), with the many-body Jastrow,
-on SD(n, n) expansions up to 126 configurations per spin, CO at 65536 walkers
-on sampled walkers, Metropolis decisions step by step, omega -> 0 against the
-no-backflow kernels, and the forms that decline backflow.
+ABI, to the same bar as the other FP64 parity tests, for both backflow
+methods: "fp64" updates every configuration from the reference (the rank <= 2
+update of eq. table, only A0 factorised) and "fp64_explicit" factorises every
+configuration.  Evaluation parity on all four molecules (several waves and a
+ragged tail), with the many-body Jastrow, on SD(n, n) expansions up to 126
+configurations per spin, CO at 65536 walkers on sampled walkers, Metropolis
+decisions step by step, the two methods against each other, omega -> 0
+against the no-backflow kernels, and the forms that decline backflow.
 """
 import numpy as np
 import pytest
@@ -28,61 +31,92 @@ def _bf(sysd, omega):
     return d
 
 
+METHODS = ["fp64", "fp64_explicit"]
+
+
+@pytest.mark.parametrize("prec", METHODS)
 @pytest.mark.parametrize("name,omega,W", [("H2", 0.35, 1000), ("LiH", 0.35, 997), ("LiH", -0.2, 130),
                                           ("Li2", 0.25, 601), ("CO", 0.25, 515), ("CO", -0.1, 67)])
-def test_backflow_eval_parity(torch_cuda, oracle_mod, name, omega, W):
+def test_backflow_eval_parity(torch_cuda, oracle_mod, name, omega, W, prec):
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
     sysd = _bf(synth.make_system(name), omega)
     X = synth.init_walkers(sysd, W, 81)
-    print(f"backflow eval {name} omega={omega} W={W}", flush=True)
+    print(f"backflow eval {name} omega={omega} W={W} {prec}", flush=True)
     s = qmc.System(sysd)
-    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
-    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"{name} backflow")
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"{name} backflow {prec}")
     s.close()
 
 
-def test_backflow_many_body(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("prec", METHODS)
+def test_backflow_many_body(torch_cuda, oracle_mod, prec):
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
     sysd = _bf(synth.with_many_body_jastrow(synth.make_system("Li2"), synth.MBJ_SEED["Li2"]), 0.3)
     X = synth.init_walkers(sysd, 203, 82)
-    print("backflow + many-body Li2 W=203", flush=True)
+    print(f"backflow + many-body Li2 W=203 {prec}", flush=True)
     s = qmc.System(sysd)
-    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
-    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, "Li2 backflow + many-body")
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"Li2 backflow + many-body {prec}")
     s.close()
 
 
+@pytest.mark.parametrize("prec", METHODS)
 @pytest.mark.parametrize("sd,W", [(2, 130), (6, 130), (10, 66)])
-def test_backflow_sd_expansion(torch_cuda, oracle_mod, sd, W):
+def test_backflow_sd_expansion(torch_cuda, oracle_mod, sd, W, prec):
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
     sysd = _bf(synth.with_sd_expansion(synth.make_system("CO"), sd, 5), 0.2)
     X = synth.init_walkers(sysd, W, 83)
-    print(f"backflow CO SD({sd}) W={W}", flush=True)
+    print(f"backflow CO SD({sd}) W={W} {prec}", flush=True)
     s = qmc.System(sysd)
-    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
-    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"CO SD({sd}) backflow")
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"CO SD({sd}) backflow {prec}")
     s.close()
 
 
-def test_backflow_full_size_co_sampled(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("prec", METHODS)
+def test_backflow_full_size_co_sampled(torch_cuda, oracle_mod, prec):
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
     sysd = _bf(synth.make_system("CO"), 0.25)
     X = synth.init_walkers(sysd, 65536, synth.WALKER_SEED["CO"])
-    print("backflow CO W=65536", flush=True)
+    print(f"backflow CO W=65536 {prec}", flush=True)
     s = qmc.System(sysd)
-    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda())]
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
     idx = np.sort(np.random.default_rng(4).choice(65536, 128, replace=False))
     idx[-1] = 65535
-    _compare(oracle_mod.OracleSystem(sysd), sysd, X[idx], lp[idx], sg[idx], el[idx], "CO backflow 64k sampled")
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X[idx], lp[idx], sg[idx], el[idx],
+             f"CO backflow 64k sampled {prec}")
     s.close()
 
 
+@pytest.mark.parametrize("name,sd,W", [("LiH", 0, 997), ("CO", 0, 515), ("CO", 8, 130)])
+def test_backflow_methods_agree(torch_cuda, name, sd, W):
+    """The low-rank update and the per-configuration factorisation give the
+    same log|Psi|, sign and E_L to rounding."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    base = synth.make_system(name)
+    sysd = _bf(synth.with_sd_expansion(base, sd, 5) if sd else base, 0.3)
+    X = torch.from_numpy(synth.init_walkers(sysd, W, 84)).cuda()
+    s = qmc.System(sysd)
+    a = [t.cpu().numpy() for t in s.eval(X)]
+    b = [t.cpu().numpy() for t in s.eval(X, precision="fp64_explicit")]
+    ok = np.isfinite(a[0]) & np.isfinite(b[0])
+    assert ok.mean() > 0.99
+    assert np.array_equal(a[1][ok], b[1][ok])
+    assert np.max(np.abs(a[0][ok] - b[0][ok]) / np.maximum(1, np.abs(b[0][ok]))) < LOG_TOL
+    de = np.abs(a[2][ok] - b[2][ok])
+    print(f"{name} SD({sd}): low-rank vs explicit median |dE_L| {np.median(de):.2e} max {de.max():.2e}")
+    assert np.median(de) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("prec", METHODS)
 @pytest.mark.parametrize("name,W,steps", [("LiH", 192, 8), ("CO", 64, 5)])
-def test_backflow_metropolis_stepwise(torch_cuda, oracle_mod, name, W, steps):
+def test_backflow_metropolis_stepwise(torch_cuda, oracle_mod, name, W, steps, prec):
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
     sysd = _bf(synth.make_system(name), 0.3)
@@ -91,13 +125,13 @@ def test_backflow_metropolis_stepwise(torch_cuda, oracle_mod, name, W, steps):
     seed, sigma = synth.PHILOX_SEED[name], 0.2
     X = synth.init_walkers(sysd, W, 7)
     lp, sg, el = o.eval(X)
-    print(f"backflow Metropolis {name} W={W} steps={steps}", flush=True)
+    print(f"backflow Metropolis {name} W={W} steps={steps} {prec}", flush=True)
     flips = 0
     for t in range(steps):
         Xo, lpo, sgo, elo, _, log = o.metropolis(X, lp, sg, el, 1, sigma, seed, step0=t, want_log=True)
         tX = torch.from_numpy(X.copy()).cuda()
         tl, ts, te = (torch.from_numpy(v.copy()).cuda() for v in (lp, sg, el))
-        acc = s.metropolis(tX, tl, ts, te, 1, sigma, seed, step0=t)
+        acc = s.metropolis(tX, tl, ts, te, 1, sigma, seed, step0=t, precision=prec)
         torch.cuda.synchronize()
         mism = acc.cpu().numpy()[:, 2] != log[0]
         if mism.any():
@@ -129,17 +163,6 @@ def test_backflow_small_omega_equals_plain(torch_cuda):
     assert np.median(np.abs(e0[ok] - e1[ok])) < 1e-10
     a.close()
     b.close()
-
-
-def test_backflow_explicit_flag_same_kernel(torch_cuda):
-    from paper_2506_09743_amd import qmc
-    torch = torch_cuda
-    sysd = _bf(synth.make_system("LiH"), 0.3)
-    X = torch.from_numpy(synth.init_walkers(sysd, 100, 2)).cuda()
-    s = qmc.System(sysd)
-    for u, v in zip(s.eval(X), s.eval(X, precision="fp64_explicit")):
-        assert torch.equal(torch.nan_to_num(u, nan=7.0), torch.nan_to_num(v, nan=7.0))
-    s.close()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x1"])
