@@ -79,14 +79,16 @@ def flops_per_walker_step(sysd) -> dict:
     return f
 
 
-def backflow_flops_per_walker_step(sysd) -> dict:
+def backflow_flops_per_walker_step(sysd, low_rank: bool = True) -> dict:
     """Algorithmic FP operations of one walker-step with the inverse backflow
-    (same counting rules), every distinct spin configuration explicitly:
-    the map q, the Jacobian blocks and their products Y_ii' = sum_j J_ij
-    J_i'j, AO values, gradients and contracted Hessians at q with the MO
-    contraction of five channels, per configuration a Gauss-Jordan
-    inverse, the Mt rows, the three traces of eq. nabla_d and the
-    other spin's Y g, per determinant its weight and cross term, and the
+    (same counting rules): the map q, the Jacobian blocks and their products
+    Y_ii' = sum_j J_ij J_i'j, AO values, gradients and contracted Hessians at
+    q with the MO contraction of five channels, per configuration its
+    determinant algebra (low_rank: the reference rows [A0 | Phi], Mt0 and
+    the residual rows Z once, then per configuration the k x k minor and the
+    rank-k update of the Mt rows; otherwise a Gauss-Jordan inverse and the Mt
+    rows per configuration), the second and third traces of eq. nabla_d and
+    the other spin's Y g, per determinant its weight and cross term, and the
     gradient assembly sum_i J_ij g_i."""
     from paper_2506_09743_amd import synth
     ne, nu, nd = synth.n_elec(sysd), int(sysd["n_up"]), int(sysd["n_dn"])
@@ -106,8 +108,12 @@ def backflow_flops_per_walker_step(sysd) -> dict:
     f["ao"] = ne * (n_sh * 20 + n_prim * ((17 if sto else 13) + 6) + nao * 40)
     f["mo"] = ne * 2 * 5 * nao * nmo
     cf = 0
-    for n, no, nc in ((nu, nd, ncfg[0]), (nd, nu, ncfg[1])):
-        cf += nc * (2 * n ** 3 + 6 * n ** 3 + 2 * n * n + 48 * n * n + 24 * n * no)
+    for spin, n, no, nc in (("up", nu, nd, ncfg[0]), ("dn", nd, nu, ncfg[1])):
+        if low_rank:
+            f["reference_" + spin] = 2 * n * n * nmo + 6 * n ** 3 + 2 * n * n + 8 * n * n * (nmo - n)
+            cf += nc * (12 + 2 * n * n * 10 + 2 * n + 48 * n * n + 24 * n * no)
+        else:
+            cf += nc * (2 * n ** 3 + 6 * n ** 3 + 2 * n * n + 48 * n * n + 24 * n * no)
     f["configurations"] = cf
     f["determinants"] = len(sysd["ci"]) * (4 + 6 * max(nu, nd))
     f["gradient"] = ne * ne * 30
@@ -359,11 +365,12 @@ BF_OMEGA = 0.1
 
 
 def backflow_bench(args, dev, seed) -> dict:
-    """The inverse backflow (omega / r_ij, omega = 0.1) on CO, FP64, every
-    configuration explicitly: Metropolis throughput at the full walker
-    count with its roofline, errors against the oracle on sampled walkers,
-    and the E_L evaluation time of the SD(n, n) expansions at 1000 walkers
-    with and without backflow."""
+    """The inverse backflow (omega / r_ij, omega = 0.1) on CO, FP64, with the
+    low-rank configuration update (QMC_FP64): Metropolis throughput at the
+    full walker count with its roofline, the same for the per-configuration
+    factorisation (QMC_FP64_EXPLICIT), errors against the oracle on sampled
+    walkers, and the E_L evaluation time of the SD(n, n) expansions at 1000
+    walkers with and without backflow."""
     import torch
     import oracle
     from paper_2506_09743_amd import qmc, synth
@@ -380,22 +387,29 @@ def backflow_bench(args, dev, seed) -> dict:
         system.metropolis(X, lp, sg, el, args.chunk, 0.2, seed, step0=step, acc=acc)
         step += args.chunk
     acc.zero_()
-    events = []
     n_launch = 3
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_launch):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        system.metropolis(X, lp, sg, el, args.chunk, 0.2, seed, step0=step, acc=acc)
-        e1.record()
-        events.append((e0, e1))
-        step += args.chunk
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    X0, lp0, sg0, el0 = X.clone(), lp.clone(), sg.clone(), el.clone()
+    timing = {}
+    for prec in ("fp64", "fp64_explicit"):
+        st = [X0.clone(), lp0.clone(), sg0.clone(), el0.clone()]
+        events = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_launch):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            system.metropolis(*st, args.chunk, 0.2, seed, step0=step + k * args.chunk, acc=acc, precision=prec)
+            e1.record()
+            events.append((e0, e1))
+        torch.cuda.synchronize()
+        timing[prec] = (time.perf_counter() - t0, float(np.mean([a.elapsed_time(b) for a, b in events])))
+        if prec == "fp64":
+            X, lp, sg, el = st
+    dt, launch_ms = timing["fp64"]
     fl = backflow_flops_per_walker_step(sysd)
+    fl_x = backflow_flops_per_walker_step(sysd, low_rank=False)
     achieved = fl["total"] * W * args.chunk / (launch_ms * 1e-3)
+    achieved_x = fl_x["total"] * W * args.chunk / (timing["fp64_explicit"][1] * 1e-3)
     idx = np.random.default_rng(0).choice(W, size=min(128, W), replace=False)
     Xn = X.cpu().numpy()[idx]
     rlp, _, rel = oracle.OracleSystem(sysd).eval(Xn)
@@ -425,18 +439,25 @@ def backflow_bench(args, dev, seed) -> dict:
         outs = [torch.empty(1000, dtype=torch.float64, device=dev) for _ in range(3)]
         t_lr = timed(lambda: qmc.qmc_eval_psi_eloc(a.handle, qmc.QMC_FP64, Xs, *outs))
         t_ex = timed(lambda: qmc.qmc_eval_psi_eloc(a.handle, qmc.QMC_FP64_EXPLICIT, Xs, *outs))
-        t_bf = timed(lambda: qmc.qmc_eval_psi_eloc(b.handle, qmc.QMC_FP64, Xs, *outs))
+        t_bl = timed(lambda: qmc.qmc_eval_psi_eloc(b.handle, qmc.QMC_FP64, Xs, *outs))
+        t_bx = timed(lambda: qmc.qmc_eval_psi_eloc(b.handle, qmc.QMC_FP64_EXPLICIT, Xs, *outs))
         sweep.append({"sd": f"SD({n},{n})", "dets": len(sd["ci"]), "eval_ms_low_rank": t_lr,
-                      "eval_ms_explicit": t_ex, "eval_ms_backflow_explicit": t_bf,
-                      "backflow_over_explicit": t_bf / t_ex})
+                      "eval_ms_explicit": t_ex, "eval_ms_backflow_low_rank": t_bl,
+                      "eval_ms_backflow_explicit": t_bx,
+                      "backflow_explicit_over_low_rank": t_bx / t_bl})
         a.close()
         b.close()
     return {"workload": f"CO, 100 determinants, {W} walkers, inverse backflow omega = {BF_OMEGA}",
+            "method": "low-rank configuration update (QMC_FP64)",
             "value": W * args.chunk * n_launch / dt, "unit": "walker-steps/s", "dtype": "f64",
             "launch_ms_mean": launch_ms, "launch_steps": args.chunk,
             "flops_per_walker_step": fl["total"],
             "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU},
+            "explicit": {"value": W * args.chunk * n_launch / timing["fp64_explicit"][0],
+                         "launch_ms_mean": timing["fp64_explicit"][1],
+                         "flops_per_walker_step": fl_x["total"],
+                         "roofline_frac": achieved_x / PEAK_FP64_VALU},
             "median_abs_dE_L": float(np.median(np.abs(gel[ok] - rel[ok]))),
             "max_abs_dE_L": float(np.max(np.abs(gel[ok] - rel[ok]))),
             "max_rel_dlogpsi": float(np.max(np.abs(glp[ok] - rlp[ok]) / np.maximum(1, np.abs(rlp[ok])))),
