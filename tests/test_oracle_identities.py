@@ -226,3 +226,39 @@ def test_excited_determinant_identities():
             lhs = np.trace(np.linalg.solve(AX, BX))
             rhs = np.trace(np.linalg.solve(A0, B0)) + np.trace(np.linalg.solve(THP, Y[np.ix_(H, P)]))
             assert np.isclose(lhs, rhs, rtol=1e-9, atol=1e-9)
+
+
+def test_backflow_low_rank_row_update():
+    """The update the low-rank backflow path relies on (eq. table applied to
+    the backflow rows): with rows electrons, A0 = Phi[:, :n], T = A0^-1 Phi,
+    an excitation putting particles P in hole slots H (A_X = Phi[:, occ]),
+    R = T[H, P] and any per-electron row matrix B (one row per electron,
+    one column per MO, e.g. the orbital gradients at the transformed
+    positions):
+      B_X A_X^-1 = B0 A0^-1 + Z[:, P] R^-1 A0^-1[H, :],   Z = B - B0 T,
+    so the Mt rows of every configuration and its first trace
+    Tr(A_X^-1 Psi_X) = Tr(A0^-1 Psi0) + Tr(Zpsi[:, P] R^-1 A0^-1[H, :])
+    come from the reference's; Z vanishes on the reference columns."""
+    n, nmo = 6, 13
+    for _ in range(20):
+        Phi = rng.standard_normal((n, nmo))
+        B = rng.standard_normal((n, nmo))
+        A0 = Phi[:, :n]
+        A0i = np.linalg.inv(A0)
+        T = A0i @ Phi
+        Z = B - B[:, :n] @ T
+        assert np.max(np.abs(Z[:, :n])) < 1e-12
+        for k in (1, 2):
+            H = sorted(rng.choice(n, size=k, replace=False))
+            P = sorted(rng.choice(range(n, nmo), size=k, replace=False))
+            occ = list(range(n))
+            for h, p in zip(H, P):
+                occ[h] = p
+            AX, BX = Phi[:, occ], B[:, occ]
+            R = T[np.ix_(H, P)]
+            lhs = BX @ np.linalg.inv(AX)
+            rhs = B[:, :n] @ A0i + Z[:, P] @ np.linalg.inv(R) @ A0i[H, :]
+            assert np.allclose(lhs, rhs, rtol=1e-9, atol=1e-9)
+            assert np.isclose(np.trace(np.linalg.solve(AX, BX)),
+                              np.trace(A0i @ B[:, :n]) + np.trace(Z[:, P] @ np.linalg.inv(R) @ A0i[H, :]),
+                              rtol=1e-9, atol=1e-9)
