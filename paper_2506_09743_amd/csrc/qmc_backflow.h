@@ -455,12 +455,8 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     double gtab[kMaxCfgBF * 3], vtab[kMaxCfgBF * 3];
     for (int q = 0; q < ncmax; ++q) {
         const bool live = q < ncfg_g;
-        double Mt[3][kMaxSpin];
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int ip = 0; ip < kMaxSpin; ++ip) Mt[b][ip] = 0.0;
         double t1 = 0.0, clog = -INFINITY, csgn = 0.0;
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
         bool singular, ok;
         if constexpr (LR) {
             // code: rank | h0 << 2 | h1 << 5 | p0 << 8 | p1 << 13, bit 20: odd
@@ -490,6 +486,8 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
                 const double zb0 = rk == 2 ? zt[p1] : 0.0, zb1 = rk == 2 ? zt[NMO + p1] : 0.0;
                 const double zb2 = rk == 2 ? zt[2 * NMO + p1] : 0.0, zbp = rk == 2 ? zt[3 * NMO + p1] : 0.0;
                 const double *hr0 = ref_g + h0 * NMO, *hr1 = ref_g + h1 * NMO;
+                // the updated row goes straight to LDS
+                double *mrow = mt_g + L.i * 3 * kMaxSpin;
 #pragma unroll
                 for (int ip = 0; ip < kMaxSpin; ++ip) {
                     if (ip >= L.nsig) break;
@@ -501,13 +499,26 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
                         d0 = Q00 * v0 + Q01 * v1;
                         d1 = Q10 * v0 + Q11 * v1;
                     }
-                    Mt[0][ip] = Mt0[0][ip] + za0 * d0 + zb0 * d1;
-                    Mt[1][ip] = Mt0[1][ip] + za1 * d0 + zb1 * d1;
-                    Mt[2][ip] = Mt0[2][ip] + za2 * d0 + zb2 * d1;
-                    if (ip == L.i) t1 = t10 + zap * d0 + zbp * d1;
+                    const double m0 = Mt0[0][ip] + za0 * d0 + zb0 * d1;
+                    const double m1 = Mt0[1][ip] + za1 * d0 + zb1 * d1;
+                    const double m2 = Mt0[2][ip] + za2 * d0 + zb2 * d1;
+                    mrow[ip] = m0;
+                    mrow[kMaxSpin + ip] = m1;
+                    mrow[2 * kMaxSpin + ip] = m2;
+                    if (ip == L.i) {
+                        g0 = m0;
+                        g1 = m1;
+                        g2 = m2;
+                        t1 = t10 + zap * d0 + zbp * d1;
+                    }
                 }
             }
         } else {
+            double Mt[3][kMaxSpin];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int ip = 0; ip < kMaxSpin; ++ip) Mt[b][ip] = 0.0;
             const int *occ = occ_g + (live ? q : 0) * kMaxSpin;
             double a[kMaxSpin];
 #pragma unroll
@@ -550,20 +561,21 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
                     t1 += irow[slot] * tab[NMO + mo];
                 }
             }
-        }
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
 #pragma unroll
-        for (int ip = 0; ip < kMaxSpin; ++ip)
-            if (ip == L.i) {
-                g0 = Mt[0][ip];
-                g1 = Mt[1][ip];
-                g2 = Mt[2][ip];
+            for (int ip = 0; ip < kMaxSpin; ++ip)
+                if (ip == L.i) {
+                    g0 = Mt[0][ip];
+                    g1 = Mt[1][ip];
+                    g2 = Mt[2][ip];
+                }
+            if (live && L.active) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int ip = 0; ip < kMaxSpin; ++ip) mt_g[(L.i * 3 + b) * kMaxSpin + ip] = Mt[b][ip];
             }
+        }
         if (live && L.active) {
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int ip = 0; ip < kMaxSpin; ++ip) mt_g[(L.i * 3 + b) * kMaxSpin + ip] = Mt[b][ip];
             double *gp = sGp + (L.grp * G + L.i) * 3;
             gp[0] = g0;
             gp[1] = g1;
@@ -583,15 +595,9 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
                 double yv0 = y[0] * m0 + y[1] * m1 + y[2] * m2;
                 double yv1 = y[3] * m0 + y[4] * m1 + y[5] * m2;
                 double yv2 = y[6] * m0 + y[7] * m1 + y[8] * m2;
-                double mi0 = 0.0, mi1 = 0.0, mi2 = 0.0;
-#pragma unroll
-                for (int t = 0; t < kMaxSpin; ++t)
-                    if (t == ip) {
-                        mi0 = Mt[0][t];
-                        mi1 = Mt[1][t];
-                        mi2 = Mt[2][t];
-                    }
-                t3 += mi0 * yv0 + mi1 * yv1 + mi2 * yv2;
+                // this lane's own row Mt_{i ., i'} as published
+                const double *mr = mt_g + L.i * 3 * kMaxSpin + ip;
+                t3 += mr[0] * yv0 + mr[kMaxSpin] * yv1 + mr[2 * kMaxSpin] * yv2;
                 const double w0 = y[0] * gq[0] + y[1] * gq[1] + y[2] * gq[2];
                 const double w1 = y[3] * gq[0] + y[4] * gq[1] + y[5] * gq[2];
                 const double w2 = y[6] * gq[0] + y[7] * gq[1] + y[8] * gq[2];
