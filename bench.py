@@ -364,6 +364,44 @@ def sd_sweep_bench(args, dev) -> list:
 BF_OMEGA = 0.1
 
 
+def kinetic_ablation_bench(dev) -> list:
+    """Jacobi-trace kinetic energy against central finite differences of Psi
+    (6 N_e + 1 Psi-only evaluations per walker, h = 1e-3), E_L of 1000
+    walkers, for the four molecules with the ground-state determinant only
+    (the setting of the paper's Fig. kinetic_bench, whose baseline is
+    automatic differentiation) and for CO with its 100 determinants."""
+    import torch
+    from paper_2506_09743_amd import qmc, synth
+
+    def timed(fn, reps=3):
+        fn()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    rows = []
+    for name, ground in (("H2", True), ("LiH", True), ("Li2", True), ("CO", True), ("CO", False)):
+        sysd = dict(synth.make_system(name))
+        if ground:
+            for k in ("occ_up", "occ_dn", "ci"):
+                sysd[k] = np.asarray(sysd[k])[:1]
+        system = qmc.System(sysd, device=0)
+        X = torch.from_numpy(synth.init_walkers(sysd, 1000, synth.WALKER_SEED[name])).to(dev)
+        outs = [torch.empty(1000, dtype=torch.float64, device=dev) for _ in range(3)]
+        t_tr = timed(lambda: qmc.qmc_eval_psi_eloc(system.handle, qmc.QMC_FP64, X, *outs))
+        t_fd = timed(lambda: qmc.qmc_eval_eloc_fd(system.handle, X, 1e-3, outs[0], outs[2]))
+        rows.append({"system": name, "dets": len(sysd["ci"]), "walkers": 1000, "eval_ms_trace": t_tr,
+                     "eval_ms_finite_differences": t_fd, "fd_over_trace": t_fd / t_tr})
+        system.close()
+    return rows
+
+
 def backflow_bench(args, dev, seed) -> dict:
     """The inverse backflow (omega / r_ij, omega = 0.1) on CO, FP64, with the
     low-rank configuration update (QMC_FP64): Metropolis throughput at the
@@ -481,6 +519,8 @@ def main():
                     help="skip the determinant-count sweep (low-rank vs explicit)")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (qmc_grad) measurement")
     ap.add_argument("--no-backflow", action="store_true", help="skip the inverse backflow measurement")
+    ap.add_argument("--no-kinetic-ablation", action="store_true",
+                    help="skip the trace vs finite-difference kinetic energy ablation")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests in the serving measurement (0: skip)")
@@ -582,6 +622,7 @@ def main():
         sd_sweep = sd_sweep_bench(args, dev)
     gradient = None if args.no_grad else grad_bench(args, dev)
     backflow = None if args.no_backflow else backflow_bench(args, dev, seed)
+    kinetic = None if args.no_kinetic_ablation else kinetic_ablation_bench(dev)
 
     fl = flops_per_walker_step(sysd)
     main_form = results["fp64"]
@@ -630,6 +671,7 @@ def main():
         "determinant_sweep": sd_sweep,
         "gradient": gradient,
         "backflow": backflow,
+        "kinetic_ablation": kinetic,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -161,6 +161,20 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
                                 double sigma, uint64_t seed, uint64_t step0,
                                 uint32_t walker_offset, double *d_acc, void *stream);
 
+/* log|Psi| and E_L of W walkers with the kinetic energy from central finite
+   differences of Psi instead of the Jacobi-trace formulas (the baseline
+   that eqs. claudia_trace / nabla_d replace; the paper's own baseline is
+   automatic differentiation, Fig. kinetic_bench): Psi is evaluated at x and
+   at x +- h e_c for each of the 3 N_e coordinates, and
+   lap Psi / Psi = sum_c (Psi(x + h e_c) - 2 Psi(x) + Psi(x - h e_c)) / (h^2 Psi(x)).
+   FP64 with the low-rank determinants; truncation error O(h^2), rounding
+   error O(eps / h^2).  d_X as in qmc_eval_psi_eloc; d_logpsi, d_eloc [W].
+   h must be finite and positive (QMC_EINVAL otherwise); systems with
+   backflow return QMC_EUNSUPPORTED.  A walker whose reference determinant
+   is exactly singular gets log|Psi| = -inf and E_L = NaN. */
+qmc_status qmc_eval_eloc_fd(qmc_system *sys, const double *d_X, int64_t W, double h, double *d_logpsi,
+                            double *d_eloc, void *stream);
+
 /* Per-walker derivatives for the optimiser and for forces, FP64 (Methods:
    eq. nabla_loss needs d log|Psi| / d theta, eq. force needs d E_L / d R and
    d ln rho / d R = 2 d log|Psi| / d R).  theta is laid out as

@@ -26,6 +26,8 @@ hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *d
 size_t grad_lds_bytes(const DevSystem &S);
 size_t explicit_lds_bytes(const DevSystem &S);
 size_t backflow_lds_bytes(const DevSystem &S, bool low_rank);
+hipError_t launch_eval_fd(const DevSystem &S, const double *X, int64_t W, double h, double *LP, double *EL,
+                          hipStream_t st);
 }  // namespace qmc
 
 using qmc::DevSystem;
@@ -663,6 +665,19 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
     hipError_t e = qmc::launch_walkers(true, walk_form(sys, precision), sys->S, d_X, d_logpsi,
                                        d_sign, d_eloc, W, n_steps, sigma, seed, step0, walker_offset,
                                        d_acc, (hipStream_t)stream);
+    return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
+}
+
+qmc_status qmc_eval_eloc_fd(qmc_system *sys, const double *d_X, int64_t W, double h, double *d_logpsi,
+                            double *d_eloc, void *stream) {
+    if (!sys || W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
+    if (!is_finite(h) || !(h > 0.0)) return QMC_EINVAL;
+    if (sys->S.bf_omega != 0.0) return QMC_EUNSUPPORTED;
+    if (W == 0) return QMC_OK;
+    if (!d_X || !d_logpsi || !d_eloc) return QMC_EINVAL;
+    DeviceGuard g(sys->device);
+    if (!g.ok) return QMC_EDEVICE;
+    hipError_t e = qmc::launch_eval_fd(sys->S, d_X, W, h, d_logpsi, d_eloc, (hipStream_t)stream);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 

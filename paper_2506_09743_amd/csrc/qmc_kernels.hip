@@ -196,6 +196,58 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSyste
     }
 }
 
+// Finite-difference kinetic energy, the baseline that the Jacobi-trace
+// formulas replace: log|Psi| at x and at x +- h e_c for each of the 3 N_e
+// coordinates (Psi only: no cofactor tables, no derivative passes), then
+// lap Psi / Psi = sum_c (Psi(x + h e_c) - 2 Psi(x) + Psi(x - h e_c)) / (h^2 Psi(x)).
+// The potential is taken at x.  FP64, low-rank determinants.
+template <int NMO>
+__global__ __launch_bounds__(kWave, 1) void k_eval_fd(DevSystem S, const double *__restrict__ X, int64_t W, double h,
+                                                      double *__restrict__ LP, double *__restrict__ EL) {
+    extern __shared__ double smem[];
+    int64_t w;
+    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+    double *wsm = smem + L.wloc * walker_lds<NMO>(S);
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    if (L.active) {
+        const double *p = X + (w * S.ne + L.e) * 3;
+        x0 = p[0];
+        x1 = p[1];
+        x2 = p[2];
+    }
+    double lp0, sg0, vpot;
+    bool bad;
+    {
+        Core<NMO> c;
+        double y0 = x0, y1 = x1, y2 = x2;
+        core_stages<NMO, double, 0, false, false, true>(S, L, wsm, y0, y1, y2, c);
+        vpot = walker_sum(L.active ? c.vpot : 0.0, S.LW) + S.vnn;
+        lp0 = walker_sum(c.J, S.LW) + c.logD_up + c.logD_dn + log(fabs(c.Ssum));
+        sg0 = c.sgn_up * c.sgn_dn * (c.Ssum < 0.0 ? -1.0 : 1.0);
+        bad = c.sing_walker > 0 || c.Ssum == 0.0;
+    }
+    double lap = 0.0;
+    for (int d = 0; d < 6 * S.ne; ++d) {
+        const int coord = d >> 1, e = coord / 3, ax = coord % 3;
+        const double step = (d & 1) ? -h : h;
+        double y0 = x0, y1 = x1, y2 = x2;
+        if (L.active && L.e == e) {
+            if (ax == 0) y0 = x0 + step;
+            else if (ax == 1) y1 = x1 + step;
+            else y2 = x2 + step;
+        }
+        Core<NMO> c;
+        core_stages<NMO, double, 0, false, false, true>(S, L, wsm, y0, y1, y2, c);
+        const double lp = walker_sum(c.J, S.LW) + c.logD_up + c.logD_dn + log(fabs(c.Ssum));
+        const double sg = c.sgn_up * c.sgn_dn * (c.Ssum < 0.0 ? -1.0 : 1.0);
+        lap += sg * sg0 * exp(lp - lp0) - 1.0;
+    }
+    if (L.wvalid && L.lw == 0) {
+        LP[w] = bad ? -INFINITY : lp0;
+        EL[w] = bad ? NAN : -0.5 * lap / (h * h) + vpot;
+    }
+}
+
 }  // namespace
 
 // ---- launch dispatch ---------------------------------------------------------
@@ -262,6 +314,21 @@ size_t backflow_lds_bytes(const DevSystem &S, bool low_rank) {
 #undef QMC_CASE
     }
     return (size_t)S.WPW * per * sizeof(double);
+}
+
+hipError_t launch_eval_fd(const DevSystem &S, const double *X, int64_t W, double h, double *LP, double *EL,
+                          hipStream_t st) {
+    const int64_t blocks = (W + S.WPW - 1) / S.WPW;
+    switch (S.nmo_pad) {
+#define QMC_CASE(N)                                                                                    \
+    case N:                                                                                            \
+        hipLaunchKernelGGL((k_eval_fd<N>), dim3((unsigned)blocks), dim3(kWave),                        \
+                           (size_t)S.WPW * walker_lds<N>(S) * sizeof(double), st, S, X, W, h, LP, EL); \
+        return hipGetLastError();
+        QMC_CASE(4) QMC_CASE(8) QMC_CASE(12) QMC_CASE(16) QMC_CASE(20) QMC_CASE(24) QMC_CASE(32)
+#undef QMC_CASE
+    }
+    return hipErrorInvalidValue;
 }
 
 size_t explicit_lds_bytes(const DevSystem &S) {

@@ -631,7 +631,9 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
 template <int NMO, bool LR>
 __host__ __device__ inline int bf_pos_offset(const DevSystem &S);
 
-template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false>
+// PSI: stop once log|Psi| is known (no cofactor tables, no adjoint vector):
+// the values a finite-difference kinetic energy needs.
+template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false, bool PSI = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
                                             double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
@@ -875,6 +877,17 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         }
     }
     const double Ssum = walker_sum(Sp, S.LW);
+    if constexpr (PSI) {
+        c.slot = slot;
+        c.Ssum = Ssum;
+        c.logD_up = logD_up;
+        c.logD_dn = logD_dn;
+        c.sgn_up = sgn_up;
+        c.sgn_dn = sgn_dn;
+        c.sing_walker = sing_walker;
+        __syncthreads();  // the tables are reused by the next evaluation
+        return;
+    }
 
     // ---- cofactor tables C_sigma[k][v] = dS / dT_sigma[k][v] ---------------
     // each lane runs its own list of contributions (same length on every

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_MIXED_FP32, "bf16": QMC_MIXED_BF16,
 
 # every symbol include/qmc.h declares
 EXPORTS = ("qmc_system_create", "qmc_system_destroy", "qmc_eval_psi_eloc", "qmc_metropolis_block",
-           "qmc_grad", "qmc_param_count", "qmc_bytes_per_walker", "qmc_status_string")
+           "qmc_grad", "qmc_eval_eloc_fd", "qmc_param_count", "qmc_bytes_per_walker",
+           "qmc_status_string")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -73,6 +74,9 @@ def lib():
         L.qmc_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p]
         L.qmc_grad.restype = C.c_int
+        L.qmc_eval_eloc_fd.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+        L.qmc_eval_eloc_fd.restype = C.c_int
         L.qmc_param_count.argtypes = [C.c_void_p]
         L.qmc_param_count.restype = C.c_int64
         L.qmc_bytes_per_walker.argtypes = [C.c_void_p, C.c_int32]
@@ -183,6 +187,12 @@ def qmc_metropolis_block(handle, precision: int, X, logpsi, sign, eloc, n_steps:
                                       _dev_ptr(acc, "acc", (W, 3)), _stream()), "qmc_metropolis_block")
 
 
+def qmc_eval_eloc_fd(handle, X, h: float, logpsi, eloc) -> None:
+    W = X.shape[0]
+    _check(lib().qmc_eval_eloc_fd(handle, _dev_ptr(X, "X"), W, float(h), _dev_ptr(logpsi, "logpsi"),
+                                  _dev_ptr(eloc, "eloc"), _stream()), "qmc_eval_eloc_fd")
+
+
 def qmc_grad(handle, X, dlogpsi=None, deloc_dtheta=None, dlogpsi_dR=None, deloc_dR=None) -> None:
     W = X.shape[0]
 
@@ -237,6 +247,14 @@ class System:
         W = X.shape[0]
         out = [torch.empty(W, dtype=torch.float64, device=X.device) for _ in range(3)]
         qmc_eval_psi_eloc(self.handle, PRECISIONS[precision], X, *out)
+        return tuple(out)
+
+    def eval_fd(self, X, h: float = 1e-3):
+        """log|Psi| and E_L with the kinetic energy from central differences of
+        Psi (step h); returns (logpsi, eloc)."""
+        import torch
+        out = [torch.empty(X.shape[0], dtype=torch.float64, device=X.device) for _ in range(2)]
+        qmc_eval_eloc_fd(self.handle, X, h, *out)
         return tuple(out)
 
     def grad(self, X):
