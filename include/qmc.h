@@ -67,9 +67,12 @@ typedef enum {
    whose CI sum is not gets finite values here.  It returns QMC_EUNSUPPORTED
    when the per-walker tables (growing with the number of distinct
    configurations) exceed the 160 KiB of LDS of a compute unit.
-   With backflow (bf_omega != 0) only FP64 exists: QMC_FP64 and
-   QMC_FP64_EXPLICIT both run the explicit per-configuration evaluation of
-   eq. nabla_d, and the mixed forms return QMC_EUNSUPPORTED. */
+   With backflow (bf_omega != 0) only FP64 exists and the mixed forms return
+   QMC_EUNSUPPORTED.  QMC_FP64 factorises the reference matrices only and
+   updates every configuration from them by the rank <= 2 identity of
+   eq. table; QMC_FP64_EXPLICIT factorises every distinct configuration.
+   Both evaluate eq. nabla_d with the cross term of eq. delta_sigma and
+   agree to rounding. */
 typedef enum {
     QMC_FP64 = 0,
     QMC_MIXED_FP32 = 1,
@@ -120,8 +123,8 @@ typedef struct {
        factor and the potential at the bare positions.  0: no backflow.
        With backflow every determinant depends on every electron; E_L then
        uses eq. nabla_d per spin block and the cross term of eq. delta_sigma,
-       with every distinct spin configuration factorised explicitly (at most
-       128 per spin). */
+       per distinct spin configuration (at most 128 per spin; see
+       qmc_precision for the two methods). */
     double bf_omega;
 } qmc_system_desc;
 
