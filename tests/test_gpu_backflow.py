@@ -165,6 +165,17 @@ def test_backflow_small_omega_equals_plain(torch_cuda):
     b.close()
 
 
+@pytest.mark.parametrize("prec", METHODS)
+def test_backflow_empty_batch(torch_cuda, prec):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    s = qmc.System(_bf(synth.make_system("CO"), 0.2))
+    X = torch.empty((0, 14, 3), dtype=torch.float64, device="cuda")
+    out = s.eval(X, precision=prec)
+    assert all(t.numel() == 0 for t in out)
+    s.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x1"])
 def test_backflow_mixed_declined(torch_cuda, prec):
     from paper_2506_09743_amd import qmc

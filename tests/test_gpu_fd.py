@@ -72,6 +72,16 @@ def test_fd_converges_to_trace(torch_cuda, oracle_mod, name):
     s.close()
 
 
+def test_fd_empty_batch(torch_cuda):
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    s = qmc.System(synth.make_system("LiH"))
+    X = torch.empty((0, 4, 3), dtype=torch.float64, device="cuda")
+    lp, el = s.eval_fd(X, 1e-3)
+    assert lp.numel() == 0 and el.numel() == 0
+    s.close()
+
+
 def test_fd_rejects(torch_cuda):
     from paper_2506_09743_amd import qmc
     torch = torch_cuda

@@ -113,3 +113,34 @@ def test_max_shape_grad_fd(torch_cuda, oracle_mod, max_system):
             gl, ge = fd(lambda d, h, a=a, k=k: d["R"].__setitem__((a, k), d["R"][a, k] + h))
             assert abs(dlR[a, k] - gl) <= 2e-6 * max(1.0, abs(gl))
             assert abs(deR[a, k] - ge) <= 2e-6 * max(1.0, abs(ge), np.max(np.abs(deR)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_explicit"])
+def test_max_shape_backflow_parity(torch_cuda, oracle_mod, precision):
+    """Both backflow methods at 8 + 8 electrons and 32 MOs (the widest
+    private MO tables and reference rows), several waves and a ragged tail."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = dict(synth.make_max_shape())
+    sysd["bf_omega"] = 0.2
+    X = synth.init_walkers(sysd, 69, 85)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=precision)]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"max shape backflow {precision}")
+    s.close()
+
+
+def test_max_shape_fd(torch_cuda, max_system):
+    """The finite-difference kinetic energy at the largest shape agrees with
+    the trace E_L on well-separated walkers to its O(h^2) error."""
+    torch = torch_cuda
+    sysd, s = max_system
+    import oracle
+    o = oracle.OracleSystem(sysd)
+    X = torch.from_numpy(good_walkers(o, sysd, 16, 86)).cuda()
+    el = s.eval(X)[2].cpu().numpy()
+    ef = s.eval_fd(X, 1e-3)[1].cpu().numpy()
+    ekin = np.array([abs(o.eval_one(x)["e_kin"]) for x in X.cpu().numpy()])
+    d = np.abs(ef - el) / np.maximum(1.0, ekin)
+    print(f"max shape FD vs trace: median {np.median(d):.2e}, max {d.max():.2e}")
+    assert np.median(d) < 1e-4
