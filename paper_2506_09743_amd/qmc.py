@@ -189,8 +189,8 @@ def qmc_metropolis_block(handle, precision: int, X, logpsi, sign, eloc, n_steps:
 
 def qmc_eval_eloc_fd(handle, X, h: float, logpsi, eloc) -> None:
     W = X.shape[0]
-    _check(lib().qmc_eval_eloc_fd(handle, _dev_ptr(X, "X"), W, float(h), _dev_ptr(logpsi, "logpsi"),
-                                  _dev_ptr(eloc, "eloc"), _stream()), "qmc_eval_eloc_fd")
+    _check(lib().qmc_eval_eloc_fd(handle, _dev_ptr(X, "X"), W, float(h), _dev_ptr(logpsi, "logpsi", (W,)),
+                                  _dev_ptr(eloc, "eloc", (W,)), _stream()), "qmc_eval_eloc_fd")
 
 
 def qmc_grad(handle, X, dlogpsi=None, deloc_dtheta=None, dlogpsi_dR=None, deloc_dR=None) -> None:
@@ -242,9 +242,15 @@ class System:
     def bytes_per_walker(self, precision="fp64") -> int:
         return qmc_bytes_per_walker(self.handle, PRECISIONS[precision])
 
+    def _walkers(self, X):
+        """X must be [W][N_e][3]: the kernels read N_e * 3 doubles per walker."""
+        if X.dim() != 3 or X.shape[1] != self.n_elec or X.shape[2] != 3:
+            raise ValueError(f"X has shape {tuple(X.shape)}, expected (W, {self.n_elec}, 3)")
+        return X.shape[0]
+
     def eval(self, X, precision="fp64"):
         import torch
-        W = X.shape[0]
+        W = self._walkers(X)
         out = [torch.empty(W, dtype=torch.float64, device=X.device) for _ in range(3)]
         qmc_eval_psi_eloc(self.handle, PRECISIONS[precision], X, *out)
         return tuple(out)
@@ -253,7 +259,7 @@ class System:
         """log|Psi| and E_L with the kinetic energy from central differences of
         Psi (step h); returns (logpsi, eloc)."""
         import torch
-        out = [torch.empty(X.shape[0], dtype=torch.float64, device=X.device) for _ in range(2)]
+        out = [torch.empty(self._walkers(X), dtype=torch.float64, device=X.device) for _ in range(2)]
         qmc_eval_eloc_fd(self.handle, X, h, *out)
         return tuple(out)
 
@@ -261,7 +267,7 @@ class System:
         """(d log|Psi|/d theta [W,P], d E_L/d theta [W,P], d log|Psi|/d R [W,A,3],
         d E_L/d R [W,A,3]) in FP64."""
         import torch
-        W, P, A = X.shape[0], self.param_count, self.n_atoms
+        W, P, A = self._walkers(X), self.param_count, self.n_atoms
         out = [torch.empty((W, P), dtype=torch.float64, device=X.device),
                torch.empty((W, P), dtype=torch.float64, device=X.device),
                torch.empty((W, A, 3), dtype=torch.float64, device=X.device),
@@ -273,6 +279,7 @@ class System:
                    acc=None, precision="fp64"):
         """In place on X, logpsi, sign, eloc, acc; returns acc."""
         import torch
+        self._walkers(X)
         if acc is None:
             acc = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
         qmc_metropolis_block(self.handle, PRECISIONS[precision], X, logpsi, sign, eloc, n_steps,

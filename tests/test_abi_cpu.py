@@ -148,3 +148,15 @@ def test_valid_backflow_passes_validation():
         with pytest.raises(qmc.QmcError) as ei:
             qmc.System(d)
         assert ei.value.status == qmc.QMC_EDEVICE
+
+
+def test_binding_rejects_misshaped_walkers():
+    """The System wrappers check X = [W][N_e][3] before any launch (a wrong
+    electron count would make the kernels read past the buffer)."""
+    import torch
+    s = qmc.System.__new__(qmc.System)
+    s.n_elec, s.n_atoms, s.handle = 4, 2, None
+    for shape in ((8, 3, 3), (8, 4, 2), (8, 12)):
+        with pytest.raises(ValueError):
+            s._walkers(torch.zeros(shape, dtype=torch.float64))
+    assert s._walkers(torch.zeros((8, 4, 3), dtype=torch.float64)) == 8
