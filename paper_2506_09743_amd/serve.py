@@ -12,7 +12,10 @@ until it retires.  Each loop iteration
 
   1. admits queued requests in arrival order while their device footprint
      (walker state from ``qmc_bytes_per_walker`` plus the system tables)
-     fits the HBM budget and a stream slot is free;
+     fits the HBM budget and a stream slot is free; a request's initial
+     walkers are drawn on its stream from its own seeded generator, and
+     its system's drawn tables come from a per-molecule cache, so admission
+     costs the scheduler thread little host time;
   2. launches the next chunk of ``chunk_steps`` Metropolis steps for every
      active request whose previous chunk has finished, each on its own
      stream, so chunks of different molecules overlap on the device;
@@ -176,8 +179,8 @@ class Server:
             sysd = synth.make_system(req.name, bond_scale=req.bond_scale)
             system = qmc.System(sysd, device=self.dev_index)
             with torch.cuda.stream(stream):
-                X = torch.from_numpy(synth.init_walkers(sysd, req.walkers, req.walker_seed)).to(
-                    self.device, non_blocking=False)
+                # drawn on the device: no host generation or copy on the scheduler thread
+                X = synth.init_walkers_device(sysd, req.walkers, req.walker_seed, self.device)
                 lp, sg, el = system.eval(X, precision=req.precision)
                 acc = torch.zeros((req.walkers, 3), dtype=torch.float64, device=self.device)
             a = _Active(req, fut, system, [X, lp, sg, el], acc, stream, need, time.perf_counter())

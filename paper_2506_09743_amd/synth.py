@@ -27,6 +27,7 @@ are not available.
 """
 from __future__ import annotations
 
+import copy
 import itertools
 import math
 
@@ -271,8 +272,20 @@ PHILOX_SEED = {"H2": 0x250609740000, "LiH": 0x250609740001,
                "CO": 0x250609740002, "Li2": 0x250609740003}
 
 
+_BASE_SYSTEMS: dict = {}
+
+
 def make_system(name: str, bond_scale: float = 1.0, seed: int | None = None) -> dict:
-    return MAKERS[name](bond_scale=bond_scale, seed=seed)
+    """A fresh copy of the named system at bond length bond_scale x
+    equilibrium.  Only the nuclear positions depend on the bond length (all
+    four molecules sit on the z axis with positions proportional to it), so
+    the drawn tables are made once per (name, seed) and copied."""
+    key = (name, seed)
+    if key not in _BASE_SYSTEMS:
+        _BASE_SYSTEMS[key] = MAKERS[name](bond_scale=1.0, seed=seed)
+    d = copy.deepcopy(_BASE_SYSTEMS[key])
+    d["R"] = d["R"] * float(bond_scale)
+    return d
 
 
 def with_sd_expansion(sysd: dict, n_active: int, seed: int) -> dict:
@@ -384,6 +397,20 @@ def init_walkers(sysd: dict, n_walkers: int, seed: int) -> np.ndarray:
     home = np.asarray(sysd["R"])[electron_atoms(sysd)]
     x = rng.standard_normal((n_walkers, n_elec(sysd), 3))
     return np.ascontiguousarray(x + home[None, :, :])
+
+
+def init_walkers_device(sysd: dict, n_walkers: int, seed: int, device):
+    """[W, N_e, 3] positions drawn on a GPU: each electron at its home nucleus
+    + N(0, I), from torch's generator seeded with ``seed`` on ``device``
+    (a different stream of numbers than init_walkers' for the same seed).
+    The draw runs on the current stream, so a request can start without a
+    host round trip."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    home = torch.as_tensor(np.asarray(sysd["R"])[electron_atoms(sysd)], dtype=torch.float64, device=device)
+    x = torch.randn((n_walkers, n_elec(sysd), 3), generator=g, dtype=torch.float64, device=device)
+    return (x + home).contiguous()
 
 
 def single_atom(Z: float, zeta: float, n_up: int = 1, n_dn: int = 0,
