@@ -30,7 +30,6 @@ a result is identical alone and in the mix.
 from __future__ import annotations
 
 import collections
-import math
 import queue
 import threading
 import time
@@ -77,13 +76,14 @@ class AdmissionError(RuntimeError):
 
 
 def reduce_accumulators(acc: np.ndarray, steps: int):
-    """Fixed-order reduction of the per-walker accumulators."""
+    """Fixed-order reduction of the per-walker accumulators (numpy's pairwise
+    summation: the same order for the same walker count, so a request's
+    result does not depend on what else runs)."""
     n = acc.shape[0] * steps
-    s1 = math.fsum(acc[:, 0].tolist())
-    s2 = math.fsum(acc[:, 1].tolist())
+    s1, s2, s3 = (float(v) for v in np.sum(np.ascontiguousarray(acc.T), axis=1))
     mean = s1 / n
     var = s2 / n - mean * mean
-    return mean, var, math.fsum(acc[:, 2].tolist()) / n
+    return mean, var, s3 / n
 
 
 class _Active:
@@ -112,6 +112,7 @@ class Server:
         self.active: list = []
         self.used = 0
         self.results: list = []
+        self._retired_systems: list = []  # destroyed once the server is idle
         self.peak_active = 0
         self.overlap_samples = 0
         self.overlap_active_sum = 0
@@ -153,6 +154,8 @@ class Server:
             self._launch()
             retired = self._retire()
             idle = not self.active and not self.pending and self.q.empty()
+            if idle or len(self._retired_systems) > 64:
+                self._destroy_retired()
             if idle and stop_when_idle and (producer is None or not producer.is_alive()):
                 break
             if not retired:
@@ -160,6 +163,13 @@ class Server:
         return self.results
 
     # -- internals ---------------------------------------------------------------
+    def _destroy_retired(self):
+        """Frees retired systems' device tables; deferred so that a retirement
+        never waits on the other requests' work in flight."""
+        for system in self._retired_systems:
+            system.close()
+        self._retired_systems = []
+
     def _drain_queue(self):
         while True:
             try:
@@ -223,8 +233,8 @@ class Server:
                 now = time.perf_counter()
                 r = Result(a.req.id, a.req.name, a.req.walkers, a.req.steps, a.req.precision, mean, var,
                            accr, now - a.req.arrival, a.admitted - a.req.arrival, a.footprint, acc)
-                a.system.close()
-                a.state = a.acc = None
+                self._retired_systems.append(a.system)
+                a.system = a.state = a.acc = None
                 self.used -= a.footprint
                 self._free_streams.append(a.stream)
                 self.results.append(r)
