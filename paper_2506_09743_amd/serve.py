@@ -21,7 +21,9 @@ until it retires.  Each loop iteration
      stream, so chunks of different molecules overlap on the device;
   3. retires requests whose last chunk finished: copies the per-walker
      accumulators to the host, reduces them in a fixed order, frees the
-     state and fulfils the future.
+     state and fulfils the future.  The system's device tables (under 1 MiB
+     each) are freed in batches, when the server is idle or 64 have piled
+     up, so a retirement never waits on other requests' work.
 
 A request's numbers depend only on its own inputs (system, walker seed,
 Philox seed, request-local walker ids), never on what else is in flight, so
