@@ -89,7 +89,9 @@ def backflow_flops_per_walker_step(sysd, low_rank: bool = True) -> dict:
     rank-k update of the Mt rows; otherwise a Gauss-Jordan inverse and the Mt
     rows per configuration), the second and third traces of eq. nabla_d and
     the other spin's Y g, per determinant its weight and cross term, and the
-    gradient assembly sum_i J_ij g_i."""
+    gradient assembly sum_i J_ij g_i.  Both traces and the cross term are
+    sums over pairs symmetric in (i, i'), so Y blocks and trace terms count
+    once per unordered same-spin pair and once per up-down pair."""
     from paper_2506_09743_amd import synth
     ne, nu, nd = synth.n_elec(sysd), int(sysd["n_up"]), int(sysd["n_dn"])
     na = len(sysd["Z"])
@@ -104,18 +106,19 @@ def backflow_flops_per_walker_step(sysd, low_rank: bool = True) -> dict:
     f["proposal"] = ne * (6 + 3 * 2 + 7)
     f["pairs"] = (ne * (ne - 1) // 2) * 25 + ne * na * 9
     f["bf_map"] = ne * (ne - 1) * 35
-    f["jacobian_products"] = ne * ne * 12 + ne ** 3 * 54
+    n_blocks = nu * (nu + 1) // 2 + nd * (nd + 1) // 2 + nu * nd  # Y blocks over unordered pairs
+    f["jacobian_products"] = ne * ne * 12 + n_blocks * ne * 54
     f["ao"] = ne * (n_sh * 20 + n_prim * ((17 if sto else 13) + 6) + nao * 40)
     f["mo"] = ne * 2 * 5 * nao * nmo
     cf = 0
     for spin, n, no, nc in (("up", nu, nd, ncfg[0]), ("dn", nd, nu, ncfg[1])):
         if low_rank:
             f["reference_" + spin] = 2 * n * n * nmo + 6 * n ** 3 + 2 * n * n + 8 * n * n * (nmo - n)
-            cf += nc * (12 + 2 * n * n * 10 + 2 * n + 48 * n * n + 24 * n * no)
+            cf += nc * (12 + 2 * n * n * 10 + 2 * n + 24 * n * (n + 1) + 12 * n * no)
         else:
-            cf += nc * (2 * n ** 3 + 6 * n ** 3 + 2 * n * n + 48 * n * n + 24 * n * no)
+            cf += nc * (2 * n ** 3 + 6 * n ** 3 + 2 * n * n + 24 * n * (n + 1) + 12 * n * no)
     f["configurations"] = cf
-    f["determinants"] = len(sysd["ci"]) * (4 + 6 * max(nu, nd))
+    f["determinants"] = len(sysd["ci"]) * (4 + 6 * ne)
     f["gradient"] = ne * ne * 30
     f["eloc"] = ne * 15 + 10
     f["accept"] = 6

@@ -25,14 +25,17 @@
 // stays.
 //
 // Work decomposition.  Lane i of a walker owns electron i as everywhere
-// else.  Its MO table at q_i (value, psi, gradient for every MO) and its
-// row of Y live in private arrays: only this lane reads them, at indices
-// that depend on the configuration.  Every distinct spin configuration is
-// factorised by the group's in-place Gauss-Jordan (both spins at once, one
-// configuration each per step); its Mt rows and g vectors go through LDS.
-// Each lane keeps, per configuration of its spin, its g_i and, per
-// configuration of the other spin, v_i = sum_{i' other} Y_ii' g_i', so the
-// cross term of a determinant is the lane sum of g_i . v_i over one spin.
+// else.  Its MO table at q_i (value, psi, gradient for every MO) lives in a
+// private array.  The pair sums above are symmetric in (i, i'), so each
+// lane holds only the Y blocks of its share of the pairs (at most 9 of
+// them, in registers): within a spin the partners i + d (mod n), d <= n/2,
+// and of the up-down pairs the half picked by the cyclic offset between the
+// two indices.  Every distinct spin configuration is factorised by the
+// group's in-place Gauss-Jordan (both spins at once, one configuration each
+// per step); its Mt rows and g vectors go through LDS.  Each lane keeps,
+// per configuration of its spin, its g_i and, per configuration of the
+// other spin, v_i = sum over its cross partners i' of Y_ii' g_i', so the
+// cross term of a determinant is the sum of g_i . v_i over all lanes.
 #pragma once
 
 namespace qmc {
@@ -308,49 +311,73 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     for (int t = 0; t < 6; ++t) sJd[6 * L.lw + t] = Jd[t];
     __syncthreads();
 
-    // ---- Y row: Y_{e,j'} = sum_m J_em J_j'm over all electrons m ---------
-    double Yr[kMaxLW * 9];
-    double Je[kMaxLW * 6];
+    // ---- Y blocks: Y_{e,j'} = sum_m J_em J_j'm over all electrons m --------
+    // Both traces summed over a spin's pairs are symmetric in (i, i'), so
+    // lane i takes the partners i' = i + d (mod n) for d <= n / 2 only, the
+    // pairs with 0 < 2d < n at weight 2.  The pairs (i up, i' down) of the
+    // cross term are split between the two groups by the cyclic offset
+    // (i' - i) mod M, M = max(n_up, n_dn): below ceil(M/2) the up lane
+    // takes the pair, otherwise the down lane.  Every block index is static,
+    // so the blocks stay in registers.
+    constexpr int kHalf = kMaxSpin / 2;
+    const int mspin = S.n_up > S.n_dn ? S.n_up : S.n_dn;
+    const int ncross = L.grp == 0 ? (mspin + 1) / 2 : mspin / 2;
+    int own_p[kHalf + 1], oth_p[kHalf];  // partner index within its group, -1: none
+#pragma unroll
+    for (int d = 0; d <= kHalf; ++d) {
+        int ip = L.i + d;
+        if (ip >= L.nsig) ip -= L.nsig;
+        own_p[d] = (L.active && 2 * d <= L.nsig) ? ip : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < kHalf; ++t) {
+        int ip = L.i + t + L.grp;
+        if (ip >= mspin) ip -= mspin;
+        oth_p[t] = (L.active && t < ncross && ip < nsig_o) ? ip : -1;
+    }
+    double Yo[kHalf + 1][9], Yc[kHalf][9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+#pragma unroll
+        for (int d = 0; d <= kHalf; ++d) Yo[d][t] = 0.0;
+#pragma unroll
+        for (int d = 0; d < kHalf; ++d) Yc[d][t] = 0.0;
+    }
     if (L.active) {
         for (int m = 0; m < S.ne; ++m) {
             const int lm = lane_of(S, m);
-            double B[6];
+            double A[6];
             if (m == L.e) {
 #pragma unroll
-                for (int t = 0; t < 6; ++t) B[t] = Jd[t];
+                for (int t = 0; t < 6; ++t) A[t] = Jd[t];
             } else {
-                jblock_pair(om, xs, sPos + 3 * lm, B);
+                jblock_pair(om, xs, sPos + 3 * lm, A);
             }
+            const double a[9] = {A[0], A[1], A[2], A[1], A[3], A[4], A[2], A[4], A[5]};
 #pragma unroll
-            for (int t = 0; t < 6; ++t) Je[6 * lm + t] = B[t];
-        }
-        for (int jp = 0; jp < S.ne; ++jp) {
-            const int lp = lane_of(S, jp);
-            double y[9];
+            for (int d = 0; d < 2 * kHalf + 1; ++d) {
+                const int ip = d <= kHalf ? own_p[d] : oth_p[d - kHalf - 1];
+                if (ip < 0) continue;
+                const int lp = (d <= kHalf ? gb_own : gb_oth) + ip;
+                double B[6];
+                if (d == 0) {
 #pragma unroll
-            for (int t = 0; t < 9; ++t) y[t] = 0.0;
-            for (int m = 0; m < S.ne; ++m) {
-                const int lm = lane_of(S, m);
-                double A[6], B[6];
-#pragma unroll
-                for (int t = 0; t < 6; ++t) A[t] = Je[6 * lm + t];
-                if (m == jp) {
+                    for (int t = 0; t < 6; ++t) B[t] = A[t];
+                } else if (lp == lm) {
 #pragma unroll
                     for (int t = 0; t < 6; ++t) B[t] = sJd[6 * lp + t];
                 } else {
                     jblock_pair(om, sPos + 3 * lp, sPos + 3 * lm, B);
                 }
-                // full 3 x 3 forms of the two symmetric blocks, y += A B
-                const double a[9] = {A[0], A[1], A[2], A[1], A[3], A[4], A[2], A[4], A[5]};
+                // y += A B with the full 3 x 3 forms of the two symmetric blocks
                 const double b[9] = {B[0], B[1], B[2], B[1], B[3], B[4], B[2], B[4], B[5]};
+                double *y = d <= kHalf ? Yo[d] : Yc[d - kHalf - 1];
 #pragma unroll
                 for (int r = 0; r < 3; ++r)
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc)
                         y[3 * r + cc] += a[3 * r] * b[cc] + a[3 * r + 1] * b[3 + cc] + a[3 * r + 2] * b[6 + cc];
             }
-#pragma unroll
-            for (int t = 0; t < 9; ++t) Yr[9 * lp + t] = y[t];
         }
     }
 
@@ -359,7 +386,7 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     {
         double Yii[6] = {1.0, 0.0, 0.0, 1.0, 0.0, 1.0};
         if (L.active) {
-            const double *y = Yr + 9 * L.lw;
+            const double *y = Yo[0];
             Yii[0] = y[0];
             Yii[1] = y[1];
             Yii[2] = y[2];
@@ -415,33 +442,44 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
 #pragma unroll
             for (int ip = 0; ip < kMaxSpin; ++ip) Mt0[b][ip] = 0.0;
         if (L.active && !ref_sing) {
+            // the reference columns' psi and gradient, read once
+            double rc[kMaxSpin][4];
 #pragma unroll
             for (int k = 0; k < kMaxSpin; ++k) {
                 if (k >= L.nsig) break;
-                const double gx = tab[2 * NMO + k], gy = tab[3 * NMO + k], gz = tab[4 * NMO + k];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) rc[k][b] = tab[(1 + b) * NMO + k];
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxSpin; ++k) {
+                if (k >= L.nsig) break;
                 const double *irow = ref_g + k * NMO;
 #pragma unroll
                 for (int ip = 0; ip < kMaxSpin; ++ip) {
                     if (ip >= L.nsig) break;
                     const double v = irow[rslots[ip]];
-                    Mt0[0][ip] += gx * v;
-                    Mt0[1][ip] += gy * v;
-                    Mt0[2][ip] += gz * v;
+                    Mt0[0][ip] += rc[k][1] * v;
+                    Mt0[1][ip] += rc[k][2] * v;
+                    Mt0[2][ip] += rc[k][3] * v;
                 }
-                t10 += irow[slot] * tab[NMO + k];
+                t10 += irow[slot] * rc[k][0];
             }
             for (int m = 0; m < NMO; ++m) {
-                double z0 = tab[2 * NMO + m], z1 = tab[3 * NMO + m], z2 = tab[4 * NMO + m], z3 = tab[NMO + m];
+                double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
                 if (m >= L.nsig) {
-                    for (int k = 0; k < L.nsig; ++k) {
+                    z0 = tab[2 * NMO + m];
+                    z1 = tab[3 * NMO + m];
+                    z2 = tab[4 * NMO + m];
+                    z3 = tab[NMO + m];
+#pragma unroll
+                    for (int k = 0; k < kMaxSpin; ++k) {
+                        if (k >= L.nsig) break;
                         const double t = ref_g[k * NMO + m];
-                        z0 -= tab[2 * NMO + k] * t;
-                        z1 -= tab[3 * NMO + k] * t;
-                        z2 -= tab[4 * NMO + k] * t;
-                        z3 -= tab[NMO + k] * t;
+                        z0 -= rc[k][1] * t;
+                        z1 -= rc[k][2] * t;
+                        z2 -= rc[k][3] * t;
+                        z3 -= rc[k][0] * t;
                     }
-                } else {
-                    z0 = z1 = z2 = z3 = 0.0;
                 }
                 zt[m] = z0;
                 zt[NMO + m] = z1;
@@ -583,25 +621,29 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         }
         __syncthreads();
 
-        // third trace and |grad log D|^2 over the spin's pairs; v for the
-        // other spin's configuration q
+        // third trace and |grad log D|^2 over this lane's share of the
+        // spin's pairs; partial v for the other spin's configuration q
         double t3 = 0.0, gg = 0.0;
         if (ok) {
-            for (int ip = 0; ip < L.nsig; ++ip) {
-                const double *y = Yr + 9 * (gb_own + ip);
+#pragma unroll
+            for (int d = 0; d <= kHalf; ++d) {
+                const int ip = own_p[d];
+                if (ip < 0) continue;
+                const double wt = (d == 0 || 2 * d == L.nsig) ? 1.0 : 2.0;
+                const double *y = Yo[d];
                 const double *mo_ = mt_g + ip * 3 * kMaxSpin;  // Mt_{i' c, .}
                 const double m0 = mo_[L.i], m1 = mo_[kMaxSpin + L.i], m2 = mo_[2 * kMaxSpin + L.i];
                 const double *gq = sGp + (L.grp * G + ip) * 3;
-                double yv0 = y[0] * m0 + y[1] * m1 + y[2] * m2;
-                double yv1 = y[3] * m0 + y[4] * m1 + y[5] * m2;
-                double yv2 = y[6] * m0 + y[7] * m1 + y[8] * m2;
+                const double yv0 = y[0] * m0 + y[1] * m1 + y[2] * m2;
+                const double yv1 = y[3] * m0 + y[4] * m1 + y[5] * m2;
+                const double yv2 = y[6] * m0 + y[7] * m1 + y[8] * m2;
                 // this lane's own row Mt_{i ., i'} as published
                 const double *mr = mt_g + L.i * 3 * kMaxSpin + ip;
-                t3 += mr[0] * yv0 + mr[kMaxSpin] * yv1 + mr[2 * kMaxSpin] * yv2;
+                t3 += wt * (mr[0] * yv0 + mr[kMaxSpin] * yv1 + mr[2 * kMaxSpin] * yv2);
                 const double w0 = y[0] * gq[0] + y[1] * gq[1] + y[2] * gq[2];
                 const double w1 = y[3] * gq[0] + y[4] * gq[1] + y[5] * gq[2];
                 const double w2 = y[6] * gq[0] + y[7] * gq[1] + y[8] * gq[2];
-                gg += g0 * w0 + g1 * w1 + g2 * w2;
+                gg += wt * (g0 * w0 + g1 * w1 + g2 * w2);
             }
         }
         if (live && L.active) {  // zeros for a singular configuration
@@ -611,8 +653,11 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         }
         if (L.active && q < ncfg_o) {
             double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-            for (int ip = 0; ip < nsig_o; ++ip) {
-                const double *y = Yr + 9 * (gb_oth + ip);
+#pragma unroll
+            for (int t = 0; t < kHalf; ++t) {
+                const int ip = oth_p[t];
+                if (ip < 0) continue;
+                const double *y = Yc[t];
                 const double *gq = sGp + ((1 - L.grp) * G + ip) * 3;
                 v0 += y[0] * gq[0] + y[1] * gq[1] + y[2] * gq[2];
                 v1 += y[3] * gq[0] + y[4] * gq[1] + y[5] * gq[2];
@@ -676,23 +721,30 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     }
     double cr = 0.0, gb0 = 0.0, gb1 = 0.0, gb2 = 0.0;
     if (L.active && !zero) {
-        // determinants alternate between the spin groups; a group's lanes
-        // sum g_i . v_i over its electrons
-        for (int n = L.grp; n < S.n_det_x; n += 2) {
-            const int2 dc = S.det_cfg[n];
-            const double w = S.ci_x[n] * sCfg[5 * dc.x + 4] * sCfg[5 * (S.n_cfg_max + dc.y) + 4] * Sinv;
-            if (w == 0.0) continue;
-            const int own = L.grp ? dc.y : dc.x, oth = L.grp ? dc.x : dc.y;
-            cr += w * (gtab[3 * own] * vtab[3 * oth] + gtab[3 * own + 1] * vtab[3 * oth + 1] +
-                       gtab[3 * own + 2] * vtab[3 * oth + 2]);
-        }
+        // per configuration q of this spin: its weight times g_i, and
+        // g_i . sum over the determinants using q of c_n D_other v_i(other)
+        // (every lane adds its share of the cross pairs)
+        const int *off = S.cfg_off + L.grp * (S.n_cfg_max + 1);
+        const double *oth_cfg = sCfg + (1 - L.grp) * S.n_cfg_max * 5;
         for (int q = 0; q < ncfg_g; ++q) {
-            const double w = cfg_g[5 * q + 2];
-            if (w == 0.0) continue;
-            gb0 += w * gtab[3 * q];
-            gb1 += w * gtab[3 * q + 1];
-            gb2 += w * gtab[3 * q + 2];
+            const double sc = cfg_g[5 * q + 4];
+            if (sc == 0.0) continue;  // singular: g and its weight vanish
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int t = off[q]; t < off[q + 1]; ++t) {
+                const int2 e = S.cfg_use[t];
+                const double w = S.ci_x[e.x] * oth_cfg[5 * e.y + 4];
+                a0 += w * vtab[3 * e.y];
+                a1 += w * vtab[3 * e.y + 1];
+                a2 += w * vtab[3 * e.y + 2];
+            }
+            const double x = gtab[3 * q], y = gtab[3 * q + 1], z = gtab[3 * q + 2];
+            const double wq = cfg_g[5 * q + 2];
+            cr += sc * (x * a0 + y * a1 + z * a2);
+            gb0 += wq * x;
+            gb1 += wq * y;
+            gb2 += wq * z;
         }
+        cr *= Sinv;
     }
     sGb[3 * L.lw] = gb0;
     sGb[3 * L.lw + 1] = gb1;
