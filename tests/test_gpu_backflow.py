@@ -5,7 +5,7 @@ methods: "fp64" updates every configuration from the reference (the rank <= 2
 update of eq. table, only A0 factorised) and "fp64_explicit" factorises every
 configuration.  Evaluation parity on all four molecules (several waves and a
 ragged tail), with the many-body Jastrow, on SD(n, n) expansions up to 126
-configurations per spin, CO at 65536 walkers on sampled walkers, Metropolis
+configurations per spin, unequal spin counts, CO at 65536 walkers on sampled walkers, Metropolis
 decisions step by step, the two methods against each other, omega -> 0
 against the no-backflow kernels, and the forms that decline backflow.
 """
@@ -46,6 +46,38 @@ def test_backflow_eval_parity(torch_cuda, oracle_mod, name, omega, W, prec):
     s = qmc.System(sysd)
     lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
     _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"{name} backflow {prec}")
+    s.close()
+
+
+def _spin_polarised(name, n_up, n_dn, sd=0):
+    """The molecule's basis and orbitals with n_up + n_dn electrons in the
+    lowest orbitals of each spin (one determinant), optionally expanded to
+    SD(sd, sd)."""
+    d = dict(synth.make_system(name))
+    d["n_up"], d["n_dn"] = n_up, n_dn
+    d["occ_up"] = np.arange(n_up, dtype=np.int32)[None, :]
+    d["occ_dn"] = np.arange(n_dn, dtype=np.int32).reshape(1, n_dn)
+    d["ci"] = np.array([1.0])
+    return synth.with_sd_expansion(d, sd, 7) if sd else d
+
+
+@pytest.mark.parametrize("prec", METHODS)
+@pytest.mark.parametrize("name,n_up,n_dn,sd,omega,W", [
+    ("LiH", 3, 1, 0, 0.3, 130), ("Li2", 4, 2, 4, 0.25, 130), ("Li2", 5, 1, 0, -0.2, 67),
+    ("Li2", 6, 0, 0, 0.3, 67), ("CO", 8, 6, 2, 0.2, 130), ("CO", 6, 8, 0, 0.2, 67)])
+def test_backflow_unequal_spins(torch_cuda, oracle_mod, name, n_up, n_dn, sd, omega, W, prec):
+    """n_up != n_dn: the up-down pairs are split between the two spin groups
+    by their cyclic offset modulo max(n_up, n_dn), odd and even, with one
+    spin empty, and with a spin of 8 electrons (its d = 4 pairs counted
+    once)."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(_spin_polarised(name, n_up, n_dn, sd), omega)
+    X = synth.init_walkers(sysd, W, 84)
+    print(f"backflow unequal spins {name} ({n_up},{n_dn}) SD{sd} W={W} {prec}", flush=True)
+    s = qmc.System(sysd)
+    lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=prec)]
+    _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"{name} ({n_up},{n_dn}) backflow {prec}")
     s.close()
 
 
