@@ -721,30 +721,30 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     }
     double cr = 0.0, gb0 = 0.0, gb1 = 0.0, gb2 = 0.0;
     if (L.active && !zero) {
-        // per configuration q of this spin: its weight times g_i, and
-        // g_i . sum over the determinants using q of c_n D_other v_i(other)
-        // (every lane adds its share of the cross pairs)
-        const int *off = S.cfg_off + L.grp * (S.n_cfg_max + 1);
-        const double *oth_cfg = sCfg + (1 - L.grp) * S.n_cfg_max * 5;
-        for (int q = 0; q < ncfg_g; ++q) {
-            const double sc = cfg_g[5 * q + 4];
-            if (sc == 0.0) continue;  // singular: g and its weight vanish
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            for (int t = off[q]; t < off[q + 1]; ++t) {
-                const int2 e = S.cfg_use[t];
-                const double w = S.ci_x[e.x] * oth_cfg[5 * e.y + 4];
-                a0 += w * vtab[3 * e.y];
-                a1 += w * vtab[3 * e.y + 1];
-                a2 += w * vtab[3 * e.y + 2];
-            }
-            const double x = gtab[3 * q], y = gtab[3 * q + 1], z = gtab[3 * q + 2];
-            const double wq = cfg_g[5 * q + 2];
-            cr += sc * (x * a0 + y * a1 + z * a2);
-            gb0 += wq * x;
-            gb1 += wq * y;
-            gb2 += wq * z;
+        // cross term: every lane adds g_i . v_i over its share of the pairs
+        // for each determinant.  The loop runs over the determinants in the
+        // same order on every lane, unrolled so that several determinants'
+        // loads are in flight at once.
+        const double *scu = sCfg + 4, *scd = sCfg + 5 * S.n_cfg_max + 4;
+#pragma unroll 4
+        for (int n = 0; n < S.n_det_x; ++n) {
+            const int2 dc = S.det_cfg[n];
+            const double w = S.ci_x[n] * scu[5 * dc.x] * scd[5 * dc.y];
+            const int own = L.grp ? dc.y : dc.x, oth = L.grp ? dc.x : dc.y;
+            const double gv = gtab[3 * own] * vtab[3 * oth] + gtab[3 * own + 1] * vtab[3 * oth + 1] +
+                              gtab[3 * own + 2] * vtab[3 * oth + 2];
+            cr += w != 0.0 ? w * gv : 0.0;  // a vanishing weight drops the term whatever g is
         }
         cr *= Sinv;
+#pragma unroll 4
+        for (int q = 0; q < ncfg_g; ++q) {
+            const double wq = cfg_g[5 * q + 2];
+            if (wq != 0.0) {
+                gb0 += wq * gtab[3 * q];
+                gb1 += wq * gtab[3 * q + 1];
+                gb2 += wq * gtab[3 * q + 2];
+            }
+        }
     }
     sGb[3 * L.lw] = gb0;
     sGb[3 * L.lw + 1] = gb1;
