@@ -130,7 +130,7 @@ __device__ __forceinline__ void reference_gauss_jordan(const DevSystem &S, const
 // two positions.
 __device__ __forceinline__ void jblock_pair(double om, const double *pi, const double *pj, double (&B)[6]) {
     const double u0 = pi[0] - pj[0], u1 = pi[1] - pj[1], u2 = pi[2] - pj[2];
-    const double rinv = 1.0 / sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+    const double rinv = rsqrt(u0 * u0 + u1 * u1 + u2 * u2);
     const double s = om * rinv;
     const double h0 = u0 * rinv, h1 = u1 * rinv, h2 = u2 * rinv;
     B[0] = -s * (1.0 - h0 * h0);
@@ -289,7 +289,7 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
             if (j == L.e) continue;
             const double *pj = sPos + 3 * lane_of(S, j);
             const double u0 = x0 - pj[0], u1 = x1 - pj[1], u2 = x2 - pj[2];
-            const double rinv = 1.0 / sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+            const double rinv = rsqrt(u0 * u0 + u1 * u1 + u2 * u2);
             const double s = om * rinv;
             q0 += s * u0;
             q1 += s * u1;
