@@ -129,7 +129,11 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_metropolis(DevSyste
     const uint32_t wid = walker_offset + (uint32_t)w;
     const double s32 = 1.0 / 4294967296.0;
     const double two_pi = 6.283185307179586;
-    for (int t = 0; t < n_steps; ++t) {
+    // With backflow every launch takes one step (the host launches the
+    // block step by step): without a loop around it the evaluation keeps
+    // the registers it has on its own.
+    const int steps = BF ? 1 : n_steps;
+    for (int t = 0; t < steps; ++t) {
         const uint64_t step = step0 + (uint64_t)t;
         uint32_t c[4] = {wid, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)L.e};
         philox4x32_10(c, k0, k1);
@@ -269,7 +273,16 @@ static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, d
     const int per = BF ? walker_lds_bf<NMO, !EXPL>(S) : (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S));
     size_t lds = (size_t)S.WPW * per * sizeof(double);
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
-    if (mc)
+    if (mc && BF) {
+        // one launch per step; the state and the running sums go through
+        // the caller's arrays between launches, so the result is the block's
+        for (int t = 0; t < n_steps; ++t) {
+            hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st,
+                               S, X, LP, SG, EL, W, 1, sigma, seed, step0 + (uint64_t)t, woff, ACC);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    } else if (mc)
         hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st,
                            S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
     else
