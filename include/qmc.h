@@ -158,7 +158,9 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
    must describe d_X (e.g. from qmc_eval_psi_eloc).  d_acc [W][3] gains, per
    step, (E_L, E_L^2, accepted) of the post-decision state; the caller zeroes
    it.  Results depend only on (seed, walker_offset + w, t), never on W or on
-   how walkers are batched. */
+   how walkers are batched.  With backflow the block is enqueued as one
+   kernel per step on `stream` (the arrays carry the state between them);
+   otherwise as one kernel. */
 qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X, double *d_logpsi,
                                 double *d_sign, double *d_eloc, int64_t W, int32_t n_steps,
                                 double sigma, uint64_t seed, uint64_t step0,
