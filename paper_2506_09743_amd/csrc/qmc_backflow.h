@@ -43,6 +43,14 @@ namespace walker {
 
 constexpr int kMaxLW = 2 * kMaxSpin;
 
+// The system tables never change while a kernel runs: read through the
+// constant address space, a load whose address is the same on every lane
+// becomes a scalar load.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *const_tab(const T *p) {
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // Walker-local lane of electron j.
 __device__ __forceinline__ int lane_of(const DevSystem &S, int j) {
     return j < S.n_up ? j : S.G + (j - S.n_up);
@@ -270,7 +278,6 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     double *piv_g = sPv + L.grp * kMaxSpin;
     double *mt_g = sMt + L.grp * 3 * G * kMaxSpin;
     double *cfg_g = sCfg + L.grp * S.n_cfg_max * 5;
-    const int *occ_g = S.cfg_occ + L.grp * S.n_cfg_max * kMaxSpin;
     const int ncfg_g = L.grp == 0 ? S.n_cfg_up : S.n_cfg_dn;
     const int ncfg_o = L.grp == 0 ? S.n_cfg_dn : S.n_cfg_up;
     const int nsig_o = L.grp == 0 ? S.n_dn : S.n_up;
@@ -499,7 +506,10 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         if constexpr (LR) {
             // code: rank | h0 << 2 | h1 << 5 | p0 << 8 | p1 << 13, bit 20: odd
             // permutation to canonical order, bit 21: identically zero
-            const int code = live ? S.cfg_exc[L.grp * S.n_cfg_max + q] : 0;
+            // both spins' codes by scalar loads, then this group's
+            const int cu = q < S.n_cfg_up ? const_tab(S.cfg_exc)[q] : 0;
+            const int cd = q < S.n_cfg_dn ? const_tab(S.cfg_exc)[S.n_cfg_max + q] : 0;
+            const int code = live ? (L.grp ? cd : cu) : 0;
             const int rk = code & 3, h0 = (code >> 2) & 7, h1 = (code >> 5) & 7;
             const int p0 = (code >> 8) & 31, p1 = (code >> 13) & 31;
             double R00 = 1.0, R01 = 0.0, R10 = 0.0, R11 = 1.0;
@@ -557,7 +567,12 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
             for (int b = 0; b < 3; ++b)
 #pragma unroll
                 for (int ip = 0; ip < kMaxSpin; ++ip) Mt[b][ip] = 0.0;
-            const int *occ = occ_g + (live ? q : 0) * kMaxSpin;
+            // both spins' occupations by scalar loads, then this group's
+            const auto *occ_u = const_tab(S.cfg_occ) + (q < S.n_cfg_up ? q : 0) * kMaxSpin;
+            const auto *occ_d = const_tab(S.cfg_occ) + (S.n_cfg_max + (q < S.n_cfg_dn ? q : 0)) * kMaxSpin;
+            int occ[kMaxSpin];
+#pragma unroll
+            for (int k = 0; k < kMaxSpin; ++k) occ[k] = L.grp ? occ_d[k] : occ_u[k];
             double a[kMaxSpin];
 #pragma unroll
             for (int k = 0; k < kMaxSpin; ++k)
@@ -726,11 +741,13 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         // same order on every lane, unrolled so that several determinants'
         // loads are in flight at once.
         const double *scu = sCfg + 4, *scd = sCfg + 5 * S.n_cfg_max + 4;
+        const auto *det_cfg = const_tab((const int *)S.det_cfg);  // (up, down) configuration pairs
+        const auto *ci_x = const_tab(S.ci_x);
 #pragma unroll 4
         for (int n = 0; n < S.n_det_x; ++n) {
-            const int2 dc = S.det_cfg[n];
-            const double w = S.ci_x[n] * scu[5 * dc.x] * scd[5 * dc.y];
-            const int own = L.grp ? dc.y : dc.x, oth = L.grp ? dc.x : dc.y;
+            const int cu = det_cfg[2 * n], cd = det_cfg[2 * n + 1];
+            const double w = ci_x[n] * scu[5 * cu] * scd[5 * cd];
+            const int own = L.grp ? cd : cu, oth = L.grp ? cu : cd;
             const double gv = gtab[3 * own] * vtab[3 * oth] + gtab[3 * own + 1] * vtab[3 * oth + 1] +
                               gtab[3 * own + 2] * vtab[3 * oth + 2];
             cr += w != 0.0 ? w * gv : 0.0;  // a vanishing weight drops the term whatever g is
