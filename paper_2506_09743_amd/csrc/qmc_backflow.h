@@ -181,18 +181,20 @@ __device__ __forceinline__ void shell_radial_h(const DevSystem &S, int p, int np
     }
 }
 
-// One component of the lane's MO table at q: comp 0 value, 1 psi
-// (Hessian contracted with Y_ii plus gradient dotted with k_i), 2..4 the
-// gradient.  For chi = P(d) R(r):
+// Channels C0 .. C0 + NC - 1 of the lane's MO table at q in one pass over
+// the shells: channel 0 value, 1 psi (Hessian contracted with Y_ii plus
+// gradient dotted with k_i), 2..4 the gradient.  For chi = P(d) R(r):
 //   d_a chi = R d_a P + P qr d_a,
 //   H chi : Y = R (dd P : Y) + 2 qr grad P^T Y d + P (qr tr Y + wr d^T Y d).
-// Returns sum_mu C[mu][m] (component of chi_mu) in out[m].
-template <int NMO>
-__device__ __forceinline__ void mo_component_bf(const DevSystem &S, int comp, double q0, double q1, double q2,
-                                                const double (&Y)[6], double k0, double k1, double k2,
-                                                double (&out)[NMO]) {
+// Returns sum_mu C[mu][m] (channel C0 + c of chi_mu) in out[c][m].
+template <int NMO, int C0, int NC>
+__device__ __forceinline__ void mo_channels_bf(const DevSystem &S, double q0, double q1, double q2,
+                                               const double (&Y)[6], double k0, double k1, double k2,
+                                               double (&out)[NC][NMO]) {
 #pragma unroll
-    for (int m = 0; m < NMO; ++m) out[m] = 0.0;
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) out[c][m] = 0.0;
     const double *crow = S.mo;
     int p = 0, atom = -1;
     double d0 = 0.0, d1 = 0.0, d2 = 0.0, r = 0.0, r2 = 0.0, rinv = 0.0;
@@ -243,14 +245,20 @@ __device__ __forceinline__ void mo_component_bf(const DevSystem &S, int comp, do
                 PY = 2.0 * Y[yi];
             }
             const double g0 = R * P0 + P * qr * d0, g1 = R * P1 + P * qr * d1, g2 = R * P2 + P * qr * d2;
-            double val;
-            if (comp == 0) val = P * R;
-            else if (comp == 1)
-                val = R * PY + 2.0 * qr * (P0 * Yd0 + P1 * Yd1 + P2 * Yd2) + P * (qr * trY + wr * dYd) +
-                      g0 * k0 + g1 * k1 + g2 * k2;
-            else val = comp == 2 ? g0 : (comp == 3 ? g1 : g2);
+            double val[NC];
 #pragma unroll
-            for (int m = 0; m < NMO; ++m) out[m] += val * crow[m];
+            for (int ch = 0; ch < NC; ++ch) {
+                const int comp = C0 + ch;
+                if (comp == 0) val[ch] = P * R;
+                else if (comp == 1)
+                    val[ch] = R * PY + 2.0 * qr * (P0 * Yd0 + P1 * Yd1 + P2 * Yd2) + P * (qr * trY + wr * dYd) +
+                              g0 * k0 + g1 * k1 + g2 * k2;
+                else val[ch] = comp == 2 ? g0 : (comp == 3 ? g1 : g2);
+            }
+#pragma unroll
+            for (int m = 0; m < NMO; ++m)
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) out[ch][m] += val[ch] * crow[m];
             crow += S.nmo_pad;
         }
     }
@@ -403,11 +411,22 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
         } else {
             q0 = q1 = q2 = 100.0;  // a far point keeps idle lanes finite
         }
-        for (int comp = 0; comp < 5; ++comp) {
-            double o[NMO];
-            mo_component_bf<NMO>(S, comp, q0, q1, q2, Yii, k0, k1, k2, o);
+        // two passes over the shells: value and psi, then the gradient
+        {
+            double o[2][NMO];
+            mo_channels_bf<NMO, 0, 2>(S, q0, q1, q2, Yii, k0, k1, k2, o);
 #pragma unroll
-            for (int m = 0; m < NMO; ++m) tab[comp * NMO + m] = o[m];
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int m = 0; m < NMO; ++m) tab[c * NMO + m] = o[c][m];
+        }
+        {
+            double o[3][NMO];
+            mo_channels_bf<NMO, 2, 3>(S, q0, q1, q2, Yii, k0, k1, k2, o);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int m = 0; m < NMO; ++m) tab[(2 + c) * NMO + m] = o[c][m];
         }
     }
 
