@@ -41,8 +41,6 @@
 namespace qmc {
 namespace walker {
 
-constexpr int kMaxLW = 2 * kMaxSpin;
-
 // The system tables never change while a kernel runs: read through the
 // constant address space, a load whose address is the same on every lane
 // becomes a scalar load.
