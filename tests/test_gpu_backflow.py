@@ -5,9 +5,11 @@ methods: "fp64" updates every configuration from the reference (the rank <= 2
 update of eq. table, only A0 factorised) and "fp64_explicit" factorises every
 configuration.  Evaluation parity on all four molecules (several waves and a
 ragged tail), with the many-body Jastrow, on SD(n, n) expansions up to 126
-configurations per spin, unequal spin counts, CO at 65536 walkers on sampled walkers, Metropolis
-decisions step by step, the two methods against each other, omega -> 0
-against the no-backflow kernels, and the forms that decline backflow.
+configurations per spin, with unequal spin counts, and for CO at 65536
+walkers on sampled walkers; Metropolis decisions step by step and a
+multi-step block against single steps; the two methods against each other,
+omega -> 0 against the no-backflow kernels, and the forms that decline
+backflow.
 """
 import numpy as np
 import pytest
@@ -176,6 +178,43 @@ def test_backflow_metropolis_stepwise(torch_cuda, oracle_mod, name, W, steps, pr
         assert np.max(np.abs(glp[same] - lpo[same]) / np.maximum(1, np.abs(lpo[same]))) < LOG_TOL
         X, lp, sg, el = Xo, lpo, sgo, elo
     assert flips == 0
+    s.close()
+
+
+@pytest.mark.parametrize("prec", METHODS)
+@pytest.mark.parametrize("name,W", [("LiH", 130), ("CO", 67)])
+def test_backflow_block_equals_single_steps(torch_cuda, oracle_mod, name, W, prec):
+    """With backflow the library enqueues a block as one kernel per step: a
+    6-step block from step0 = 3 equals six one-step calls exactly (positions,
+    log|Psi|, sign, E_L and the running sums), and its end state matches the
+    oracle's 6-step chain."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = _bf(synth.make_system(name), 0.3)
+    o = oracle_mod.OracleSystem(sysd)
+    s = qmc.System(sysd)
+    seed, sigma, steps, step0 = synth.PHILOX_SEED[name], 0.2, 6, 3
+    X = synth.init_walkers(sysd, W, 11)
+    lp, sg, el = o.eval(X)
+    print(f"backflow block vs single steps {name} W={W} {prec}", flush=True)
+
+    def state():
+        return [torch.from_numpy(v.copy()).cuda() for v in (X, lp, sg, el)]
+
+    a = state()
+    acc_a = s.metropolis(*a, steps, sigma, seed, step0=step0, precision=prec)
+    b = state()
+    acc_b = torch.zeros((W, 3), dtype=torch.float64, device="cuda")
+    for t in range(steps):
+        s.metropolis(*b, 1, sigma, seed, step0=step0 + t, acc=acc_b, precision=prec)
+    torch.cuda.synchronize()
+    for u, v in zip(a + [acc_a], b + [acc_b]):
+        assert torch.equal(u, v)
+    Xo, lpo, _, _, acc_o, _ = o.metropolis(X, lp, sg, el, steps, sigma, seed, step0=step0)
+    assert np.array_equal(acc_a.cpu().numpy()[:, 2], acc_o[:, 2])
+    assert np.max(np.abs(a[0].cpu().numpy() - Xo)) < 1e-12
+    glp = a[1].cpu().numpy()
+    assert np.max(np.abs(glp - lpo) / np.maximum(1, np.abs(lpo))) < LOG_TOL
     s.close()
 
 
