@@ -2,7 +2,8 @@
 (16-lane walkers), 32 MOs (the widest column bucket) and 32 AOs (the
 matrix-core limit), with d shells and contracted Gaussians.  FP64 and
 explicit-method parity against the oracle, the mixed forms' errors,
-Metropolis decisions step by step, and the adjoint against oracle finite
+Metropolis decisions step by step (also with backflow, where a block of
+steps must equal single steps), and the adjoint against oracle finite
 differences for a sample of parameters."""
 import numpy as np
 import pytest
@@ -127,6 +128,52 @@ def test_max_shape_backflow_parity(torch_cuda, oracle_mod, precision):
     s = qmc.System(sysd)
     lp, sg, el = [t.cpu().numpy() for t in s.eval(torch.from_numpy(X).cuda(), precision=precision)]
     _compare(oracle_mod.OracleSystem(sysd), sysd, X, lp, sg, el, f"max shape backflow {precision}")
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_explicit"])
+def test_max_shape_backflow_metropolis(torch_cuda, oracle_mod, precision):
+    """Backflow Metropolis at 8 + 8 electrons and 32 MOs: a 3-step block
+    (one kernel per step) equals three chained one-step calls exactly, and
+    each step's decisions and states match the oracle's, ties aside."""
+    from paper_2506_09743_amd import qmc
+    torch = torch_cuda
+    sysd = dict(synth.make_max_shape())
+    sysd["bf_omega"] = 0.2
+    s = qmc.System(sysd)
+    o = oracle_mod.OracleSystem(sysd)
+    seed, sigma, W = 0x2506097400FE, 0.1, 40
+    X = synth.init_walkers(sysd, W, 86)
+    lp, sg, el = o.eval(X)
+    print(f"max shape backflow Metropolis {precision}", flush=True)
+
+    def state(*vals):
+        return [torch.from_numpy(np.array(v, copy=True)).cuda() for v in vals]
+
+    blk = state(X, lp, sg, el)
+    acc_blk = s.metropolis(*blk, 3, sigma, seed, step0=0, precision=precision)
+    one = state(X, lp, sg, el)
+    acc_one = torch.zeros((W, 3), dtype=torch.float64, device="cuda")
+    for t in range(3):
+        s.metropolis(*one, 1, sigma, seed, step0=t, acc=acc_one, precision=precision)
+    torch.cuda.synchronize()
+    for u, v in zip(blk + [acc_blk], one + [acc_one]):
+        assert torch.equal(u, v)
+    for t in range(3):
+        Xo, lpo, sgo, elo, _, log = o.metropolis(X, lp, sg, el, 1, sigma, seed, step0=t, want_log=True)
+        tX, tl, ts, te = state(X, lp, sg, el)
+        acc = s.metropolis(tX, tl, ts, te, 1, sigma, seed, step0=t, precision=precision)
+        torch.cuda.synchronize()
+        mism = acc.cpu().numpy()[:, 2] != log[0]
+        if mism.any():
+            margin = _one_step_margin(o, sysd, X, lp, seed, t, sigma, oracle_mod)
+            assert np.all(margin[mism] < 1e-9)
+        same = ~mism
+        assert np.max(np.abs(tX.cpu().numpy()[same] - Xo[same])) < 1e-12
+        glp = tl.cpu().numpy()
+        ok = same & np.isfinite(lpo)
+        assert np.max(np.abs(glp[ok] - lpo[ok]) / np.maximum(1, np.abs(lpo[ok]))) < LOG_TOL
+        X, lp, sg, el = Xo, lpo, sgo, elo
     s.close()
 
 
