@@ -246,7 +246,7 @@ def many_body_bench(sysd, args, dev, seed) -> dict:
     system = qmc.System(sysd_m, device=0)
     X = torch.from_numpy(synth.init_walkers(sysd_m, W, synth.WALKER_SEED[args.system])).to(dev)
     lp, sg, el = system.eval(X)
-    acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+    acc = torch.zeros((W, qmc.ACC_COLS), dtype=torch.float64, device=dev)
     step = 0
     for _ in range(0, args.burnin + args.warmup, args.chunk):
         system.metropolis(X, lp, sg, el, args.chunk, 0.2, seed, step0=step, acc=acc)
@@ -356,7 +356,7 @@ def sd_sweep_bench(args, dev) -> list:
                             "explicit_over_low_rank": t_exp / t_tab}
             if W == args.walkers:
                 lp, sg, el = system.eval(X)
-                acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+                acc = torch.zeros((W, qmc.ACC_COLS), dtype=torch.float64, device=dev)
                 t_mc = timed(lambda: system.metropolis(X, lp, sg, el, args.chunk, 0.2, 1, acc=acc))
                 row[f"W{W}"]["metropolis_walker_steps_per_s"] = W * args.chunk / (t_mc * 1e-3)
         rows.append(row)
@@ -422,7 +422,7 @@ def backflow_bench(args, dev, seed) -> dict:
     system = qmc.System(sysd, device=0)
     X = torch.from_numpy(synth.init_walkers(sysd, W, synth.WALKER_SEED["CO"])).to(dev)
     lp, sg, el = system.eval(X)
-    acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+    acc = torch.zeros((W, qmc.ACC_COLS), dtype=torch.float64, device=dev)
     step = 0
     for _ in range(2):  # burn-in and warm-up
         system.metropolis(X, lp, sg, el, args.chunk, 0.2, seed, step0=step, acc=acc)
@@ -568,7 +568,7 @@ def main():
     # equilibrate in FP64
     lp, sg, el = system.eval(X)
     state = [X, lp, sg, el]
-    acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+    acc = torch.zeros((W, qmc.ACC_COLS), dtype=torch.float64, device=dev)
     step = run_steps(state, args.burnin, 0, "fp64", acc)
     torch.cuda.synchronize()
     X_eq = X.clone()
@@ -579,7 +579,7 @@ def main():
         st = [X_eq.clone(), lp_eq.clone(), sg_eq.clone(), el_eq.clone()]
         if form != "fp64":  # the mixed chain carries its own log|Psi| and E_L
             st[1], st[2], st[3] = system.eval(st[0], precision=form)
-        acc = torch.zeros((W, 3), dtype=torch.float64, device=dev)
+        acc = torch.zeros((W, qmc.ACC_COLS), dtype=torch.float64, device=dev)
         s0 = run_steps(st, args.warmup, step, form, acc)
         acc.zero_()
         events = []

@@ -28,8 +28,14 @@
  *     has been synchronised.
  *   - One handle is used from one host thread at a time.
  *   - No call aborts, throws or prints.  Argument checks run before any
- *     launch and return QMC_EINVAL; an unsupported shape returns
+ *     launch and return QMC_EINVAL (QMC_ENONFINITE for a NaN or infinite
+ *     value where a finite one is required); an unsupported shape returns
  *     QMC_EUNSUPPORTED; a HIP runtime failure returns QMC_EDEVICE.
+ *   - Walker data are never an error: a walker whose state has no finite
+ *     log|Psi| or E_L (NaN or infinite positions, coincident same-spin
+ *     electrons, an exactly singular reference matrix) is reported through
+ *     the Metropolis accumulators' non-finite count and left out of their
+ *     sums.
  */
 #ifndef QMC_H
 #define QMC_H
@@ -46,18 +52,30 @@ typedef enum {
     QMC_EINVAL = -1,        /* invalid argument or descriptor */
     QMC_ENOMEM = -2,        /* device allocation failed */
     QMC_EDEVICE = -3,       /* HIP runtime error (or no device) */
-    QMC_EUNSUPPORTED = -4   /* valid input outside the compiled limits */
+    QMC_EUNSUPPORTED = -4,  /* valid input outside the compiled limits */
+    QMC_ENONFINITE = -5     /* a host argument or descriptor value that must be
+                               finite is NaN or infinite (nothing launched) */
 } qmc_status;
 
 /* Arithmetic of a call.  QMC_FP64: everything in FP64.  The mixed forms
-   evaluate AO values in FP32 and keep the Slater inverse, determinant
-   ratios, Jacobi traces, Jastrow and E_L in FP64; they differ in the AO->MO
-   contractions:
+   (Methods, AO and MO layers) evaluate the AO values and derivatives in FP32
+   (displacements from the nuclei formed in FP64, then rounded) and the MO
+   values phi = sum C chi with FP32 accumulation; everything else is FP64:
+   the proposal and accept test, the Pade Jastrow and Coulomb pair terms,
+   the Slater inverse and determinant ratios, the cofactors and adjoint
+   vectors, the Jacobi-trace contraction of the AO derivatives (AO weights
+   t = C a_e and the products t * (grad, lap) chi) and E_L.  They differ in
+   the MO value contraction:
      QMC_MIXED_FP32     FP32 vector FMAs;
      QMC_MIXED_BF16     BF16 matrix-core products with FP32 accumulation,
                         each operand split into high and low BF16 parts
                         (hi*hi + hi*lo + lo*hi, about 16 significant bits);
      QMC_MIXED_BF16_X1  one BF16 product per pair (8 significant bits).
+   A walker whose kinetic energy from the reduced-precision orbitals is not
+   finite or exceeds 3e4 Ha in magnitude is evaluated again with FP64
+   orbitals (those are walkers with an electron inside the tightest
+   primitives, where cancelling kinetic terms amplify the orbital rounding);
+   its results are then the FP64 form's.
    The BF16 forms need n_ao <= 32.
    QMC_FP64_EXPLICIT is FP64 with a different determinant method, kept for
    comparison: every distinct spin configuration of the CI expansion is
@@ -155,12 +173,15 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
    + w, t low word, t high word, electron)); it accepts when
    u < exp(2 (log|Psi'| - log|Psi|)), u from counter word 3 = N_e, and then
    takes (X', log|Psi'|, sign', E_L').  On entry d_logpsi, d_sign and d_eloc
-   must describe d_X (e.g. from qmc_eval_psi_eloc).  d_acc [W][3] gains, per
-   step, (E_L, E_L^2, accepted) of the post-decision state; the caller zeroes
-   it.  Results depend only on (seed, walker_offset + w, t), never on W or on
-   how walkers are batched.  With backflow the block is enqueued as one
-   kernel per step on `stream` (the arrays carry the state between them);
-   otherwise as one kernel. */
+   must describe d_X (e.g. from qmc_eval_psi_eloc).  d_acc [W][4] gains, per
+   step, from the post-decision state: (E_L, E_L^2, accepted, 0) when its
+   log|Psi| and E_L are finite, else (0, 0, accepted, 1): column 3 counts the
+   steps left out of the sums.  The caller zeroes d_acc before a block's
+   first call.  Results depend only on (seed, walker_offset + w, t), never on
+   W or on how walkers are batched.  sigma must be finite (QMC_ENONFINITE)
+   and >= 0 (QMC_EINVAL).  With backflow the block is enqueued as one kernel
+   per step on `stream` (the arrays carry the state between them); otherwise
+   as one kernel. */
 qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X, double *d_logpsi,
                                 double *d_sign, double *d_eloc, int64_t W, int32_t n_steps,
                                 double sigma, uint64_t seed, uint64_t step0,
@@ -202,8 +223,19 @@ qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlo
 int64_t qmc_param_count(const qmc_system *sys);
 
 /* Device bytes one walker occupies across a Metropolis block (positions,
-   log|Psi|, sign, E_L, accumulators), for admission control. */
+   log|Psi|, sign, E_L, the four accumulators), for admission control. */
 size_t qmc_bytes_per_walker(const qmc_system *sys, int32_t precision);
+
+/* Reduction of a block's accumulators over its walkers (the Monte Carlo
+   estimate of eq. Ev): d_out[5] = (sum of column 0, sum of column 1, sum of
+   column 2, sum of column 3, number of walkers with a non-zero column 3) of
+   d_acc [W][4].  The summation order is fixed by W alone (a strided
+   sequential pass per thread of one work-group, then a fixed binary tree),
+   so the result is the same for the same accumulators wherever and however
+   they were produced.  Mean energy = d_out[0] / (W n_steps - d_out[3]).
+   d_out is caller-owned device memory; asynchronous on `stream`; W = 0
+   writes zeros.  No workspace. */
+qmc_status qmc_reduce_accumulators(const double *d_acc, int64_t W, double *d_out, void *stream);
 
 /* Static text for a status code. */
 const char *qmc_status_string(qmc_status status);

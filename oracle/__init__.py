@@ -197,7 +197,7 @@ class OracleSystem:
         sg = np.array(sign, dtype=np.float64, copy=True)
         el = np.array(eloc, dtype=np.float64, copy=True)
         W = X.shape[0]
-        acc = np.zeros((W, 3)) if acc is None else np.array(acc, dtype=np.float64, copy=True)
+        acc = np.zeros((W, 4)) if acc is None else np.array(acc, dtype=np.float64, copy=True)
         log = np.zeros((n_steps, W), dtype=np.uint8) if want_log else None
         self.L.or_metropolis(self.ref, _p(X), _p(lp), _p(sg), _p(el), W, int(n_steps),
                             float(sigma), C.c_uint64(seed), C.c_uint64(step0),

@@ -762,9 +762,15 @@ void or_metropolis(const or_system *s, double *X, double *logpsi, double *sign, 
                 sign[w] = d.sign;
                 eloc[w] = d.eloc;
             }
-            acc[3 * w + 0] += eloc[w];
-            acc[3 * w + 1] += eloc[w] * eloc[w];
-            acc[3 * w + 2] += accept ? 1.0 : 0.0;
+            /* the Monte Carlo mean of eq. Ev runs over the steps whose state
+               has a finite log|Psi| and E_L; the others are only counted */
+            if (isfinite(eloc[w]) && isfinite(logpsi[w])) {
+                acc[4 * w + 0] += eloc[w];
+                acc[4 * w + 1] += eloc[w] * eloc[w];
+            } else {
+                acc[4 * w + 3] += 1.0;
+            }
+            acc[4 * w + 2] += accept ? 1.0 : 0.0;
             if (accept_log) accept_log[(size_t)t * W + w] = (uint8_t)accept;
         }
         free(xp);

@@ -80,8 +80,10 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 void or_proposal(int n_elec, uint64_t seed, uint32_t walker_id, uint64_t step,
                  double *z, double *u_accept);
 
-/* Metropolis block: n_steps all-electron moves per walker.  acc[W][3] gains
-   (sum E_L, sum E_L^2, accepted count) of the post-decision state.
+/* Metropolis block: n_steps all-electron moves per walker.  acc[W][4] gains
+   (sum E_L, sum E_L^2, accepted count, non-finite count) of the
+   post-decision state: a state whose log|Psi| or E_L is not finite adds 1 to
+   the last column and nothing to the sums.
    accept_log (nullable) receives [n_steps][W] bytes. */
 void or_metropolis(const or_system *s, double *X, double *logpsi, double *sign,
                    double *eloc, int64_t W, int n_steps, double sigma,

@@ -28,6 +28,7 @@ size_t explicit_lds_bytes(const DevSystem &S);
 size_t backflow_lds_bytes(const DevSystem &S, bool low_rank);
 hipError_t launch_eval_fd(const DevSystem &S, const double *X, int64_t W, double h, double *LP, double *EL,
                           hipStream_t st);
+hipError_t launch_reduce_acc(const double *acc, int64_t W, double *out, hipStream_t st);
 }  // namespace qmc
 
 using qmc::DevSystem;
@@ -153,7 +154,7 @@ qmc_status validate(const qmc_system_desc *d) {
     if (d->normalize != 0 && d->normalize != 1) return QMC_EINVAL;
     for (int a = 0; a < d->n_atoms; ++a) {
         if (!is_finite(d->Z[a]) || !is_finite(d->R[3 * a]) || !is_finite(d->R[3 * a + 1]) || !is_finite(d->R[3 * a + 2]))
-            return QMC_EINVAL;
+            return QMC_ENONFINITE;
     }
     int n_prim = 0;
     for (int s = 0; s < d->n_shells; ++s) {
@@ -162,35 +163,38 @@ qmc_status validate(const qmc_system_desc *d) {
         if (d->basis == QMC_GTO && d->shell_kn[s] != 0) return QMC_EINVAL;
         n_prim += d->shell_nprim[s];
     }
-    for (int p = 0; p < n_prim; ++p)
-        if (!(d->prim_exp[p] > 0.0) || !is_finite(d->prim_exp[p]) || !is_finite(d->prim_coef[p]))
-            return QMC_EINVAL;
+    for (int p = 0; p < n_prim; ++p) {
+        if (!is_finite(d->prim_exp[p]) || !is_finite(d->prim_coef[p])) return QMC_ENONFINITE;
+        if (!(d->prim_exp[p] > 0.0)) return QMC_EINVAL;
+    }
     int n_ao = 0;
     for (int s = 0; s < d->n_shells; ++s) n_ao += (d->shell_l[s] + 1) * (d->shell_l[s] + 2) / 2;
     for (int64_t q = 0; q < (int64_t)n_ao * d->n_mo; ++q)
-        if (!is_finite(d->mo_coef[q])) return QMC_EINVAL;
+        if (!is_finite(d->mo_coef[q])) return QMC_ENONFINITE;
     for (int n = 0; n < d->n_det; ++n) {
-        if (!is_finite(d->ci[n])) return QMC_EINVAL;
+        if (!is_finite(d->ci[n])) return QMC_ENONFINITE;
         for (int k = 0; k < d->n_up; ++k)
             if (d->occ_up[n * d->n_up + k] < 0 || d->occ_up[n * d->n_up + k] >= d->n_mo) return QMC_EINVAL;
         for (int k = 0; k < d->n_dn; ++k)
             if (d->occ_dn[n * d->n_dn + k] < 0 || d->occ_dn[n * d->n_dn + k] >= d->n_mo) return QMC_EINVAL;
     }
-    if (!is_finite(d->jas_a_par) || !is_finite(d->jas_a_anti) || !is_finite(d->jas_b) || d->jas_b < 0.0)
-        return QMC_EINVAL;
+    if (!is_finite(d->jas_a_par) || !is_finite(d->jas_a_anti) || !is_finite(d->jas_b)) return QMC_ENONFINITE;
+    if (d->jas_b < 0.0) return QMC_EINVAL;
     if (d->jas_en)
         for (int a = 0; a < d->n_atoms; ++a) {
             const double *w = d->jas_en + 3 * a;
-            if (!is_finite(w[0]) || !is_finite(w[1]) || !is_finite(w[2]) || w[2] < 0.0) return QMC_EINVAL;
+            if (!is_finite(w[0]) || !is_finite(w[1]) || !is_finite(w[2])) return QMC_ENONFINITE;
+            if (w[2] < 0.0) return QMC_EINVAL;
         }
     if (d->jas_een_n < 0 || d->jas_een_n > qmc::kMaxEen) return QMC_EINVAL;
     if (d->jas_een_n > 0 && !d->jas_een) return QMC_EINVAL;
     for (int m = 0; m < d->jas_een_n; ++m)
         for (int k = 0; k < 7; ++k) {
             const double v = d->jas_een[7 * m + k];
-            if (!is_finite(v) || ((k == 2 || k == 4 || k == 6) && v < 0.0)) return QMC_EINVAL;
+            if (!is_finite(v)) return QMC_ENONFINITE;
+            if ((k == 2 || k == 4 || k == 6) && v < 0.0) return QMC_EINVAL;
         }
-    if (!is_finite(d->bf_omega)) return QMC_EINVAL;
+    if (!is_finite(d->bf_omega)) return QMC_ENONFINITE;
     return QMC_OK;
 }
 
@@ -256,6 +260,7 @@ const char *qmc_status_string(qmc_status s) {
         case QMC_ENOMEM: return "device allocation failed";
         case QMC_EDEVICE: return "HIP device error";
         case QMC_EUNSUPPORTED: return "unsupported by this build";
+        case QMC_ENONFINITE: return "non-finite argument";
     }
     return "unknown status";
 }
@@ -656,7 +661,8 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
                                 double *d_acc, void *stream) {
     qmc_status st = check_walk_args(sys, precision, W);
     if (st != QMC_OK) return st;
-    if (n_steps < 0 || !is_finite(sigma) || sigma < 0.0) return QMC_EINVAL;
+    if (!is_finite(sigma)) return QMC_ENONFINITE;
+    if (n_steps < 0 || sigma < 0.0) return QMC_EINVAL;
     if ((uint64_t)walker_offset + (uint64_t)W > 0x100000000ull) return QMC_EINVAL;
     if (W == 0 || n_steps == 0) return QMC_OK;
     if (!d_X || !d_logpsi || !d_sign || !d_eloc || !d_acc) return QMC_EINVAL;
@@ -671,7 +677,8 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
 qmc_status qmc_eval_eloc_fd(qmc_system *sys, const double *d_X, int64_t W, double h, double *d_logpsi,
                             double *d_eloc, void *stream) {
     if (!sys || W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
-    if (!is_finite(h) || !(h > 0.0)) return QMC_EINVAL;
+    if (!is_finite(h)) return QMC_ENONFINITE;
+    if (!(h > 0.0)) return QMC_EINVAL;
     if (sys->S.bf_omega != 0.0) return QMC_EUNSUPPORTED;
     if (W == 0) return QMC_OK;
     if (!d_X || !d_logpsi || !d_eloc) return QMC_EINVAL;
@@ -700,8 +707,14 @@ int64_t qmc_param_count(const qmc_system *sys) { return sys ? sys->n_params : -1
 size_t qmc_bytes_per_walker(const qmc_system *sys, int32_t precision) {
     (void)precision;
     if (!sys) return 0;
-    // positions + (log|Psi|, sign, E_L) + three accumulators, all FP64
-    return (size_t)sys->S.ne * 3 * sizeof(double) + 6 * sizeof(double);
+    // positions + (log|Psi|, sign, E_L) + four accumulators, all FP64
+    return (size_t)sys->S.ne * 3 * sizeof(double) + 7 * sizeof(double);
+}
+
+qmc_status qmc_reduce_accumulators(const double *d_acc, int64_t W, double *d_out, void *stream) {
+    if (W < 0 || W > (int64_t)0x7FFFFFFF || !d_out || (W > 0 && !d_acc)) return QMC_EINVAL;
+    hipError_t e = qmc::launch_reduce_acc(d_acc, W, d_out, (hipStream_t)stream);
+    return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 
 }  // extern "C"

@@ -225,7 +225,10 @@ __device__ __forceinline__ double rcp_ge1(double x) {
 
 template <typename RT> __device__ __forceinline__ RT rt_exp(RT x);
 template <> __device__ __forceinline__ double rt_exp<double>(double x) { return exp_f64(x); }
-template <> __device__ __forceinline__ float rt_exp<float>(float x) { return expf(x); }
+// FP32: the hardware base-2 exponential of x log2(e)
+template <> __device__ __forceinline__ float rt_exp<float>(float x) {
+    return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+}
 
 template <typename RT> __device__ __forceinline__ const RT *mo_table(const DevSystem &S);
 template <> __device__ __forceinline__ const double *mo_table<double>(const DevSystem &S) { return S.mo; }
@@ -322,16 +325,16 @@ __device__ __forceinline__ void mo_values(const DevSystem &S, double x0, double 
 // d log Sigma / d phi_m(r_e) and t_mu = sum_m C[mu][m] a_e[m], both are
 // sum_mu t_mu (grad, lap) chi_mu(r_e); for chi = P R:
 //   grad chi = R grad P + P (R'/r) d,   lap chi = R lap P + P (R'' + (2l+2) R'/r).
+// This contraction is the Jacobi trace: the weights t and the products
+// t (grad, lap) chi are FP64 in every form; RT is the arithmetic of the AO
+// derivative factors (FP32 in the mixed forms).
 template <int NMO, typename RT>
 __device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, double x1, double x2,
                                              const double (&av)[NMO], double &g0, double &g1,
                                              double &g2, double &lap) {
-    const RT *C = mo_table<RT>(S);
-    RT a[NMO];
-#pragma unroll
-    for (int m = 0; m < NMO; ++m) a[m] = RT(av[m]);
+    const double *C = S.mo;
     int p = 0;
-    const RT *crow = C;
+    const double *crow = C;
     double G0 = 0.0, G1 = 0.0, G2 = 0.0, L = 0.0;
     int atom = -1;
     RT dx = RT(0), dy = RT(0), dz = RT(0), r2 = RT(0), r = RT(0), rinv = RT(0);
@@ -352,9 +355,9 @@ __device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, doub
         p += si.w;
         const int nc = (si.y + 1) * (si.y + 2) / 2;
         for (int c = 0; c < nc; ++c) {
-            RT t = RT(0);
+            double t = 0.0;
 #pragma unroll
-            for (int m = 0; m < NMO; ++m) t += crow[m] * a[m];
+            for (int m = 0; m < NMO; ++m) t += crow[m] * av[m];
             crow += S.nmo_pad;
             // monomial, its gradient and Laplacian
             RT P, Px, Py, Pz, PL;
@@ -379,10 +382,10 @@ __device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, doub
                 PL = iu == iv ? RT(2) : RT(0);
             }
             const RT PRd = P * Rd;
-            G0 += double(t * (Rv * Px + PRd * dx));
-            G1 += double(t * (Rv * Py + PRd * dy));
-            G2 += double(t * (Rv * Pz + PRd * dz));
-            L += double(t * (Rv * PL + P * Rl));
+            G0 += t * double(Rv * Px + PRd * dx);
+            G1 += t * double(Rv * Py + PRd * dy);
+            G2 += t * double(Rv * Pz + PRd * dz);
+            L += t * double(Rv * PL + P * Rl);
         }
     }
     g0 = G0;
@@ -392,8 +395,8 @@ __device__ __forceinline__ void sigma_derivs(const DevSystem &S, double x0, doub
 }
 
 // ---- BF16 matrix-core contractions (mixed form) ------------------------------
-// A wave applies a fixed 32 x 32 matrix M (C^T for MO values, C for the AO
-// weights t = C a_e) to one 32-vector per lane with v_mfma_f32_16x16x32_bf16:
+// A wave applies the fixed 32 x 32 matrix M = C^T (MO values from AO values)
+// to one 32-vector per lane with v_mfma_f32_16x16x32_bf16:
 // output tile t (16 rows of M) times the vectors of lane quarter q (16 lanes)
 // is one MFMA.  Vectors are staged through LDS so that lane 16 g + j supplies
 // elements 8 g .. 8 g + 7 of lane 16 q + j's vector; the 16 x 16 result lands
@@ -503,80 +506,6 @@ __device__ __forceinline__ void mo_values_mfma(const DevSystem &S, int lane, voi
     __syncthreads();
 }
 
-// AO weights t_mu = sum_m C[mu][m] a_e[m] of every lane on the matrix cores;
-// on return st.out[lane][mu] holds them (read before the next staging).
-template <int NMO, int SPLIT>
-__device__ __forceinline__ void ao_weights_mfma(const DevSystem &S, int lane, void *stage_base,
-                                                const double (&av)[NMO]) {
-    const Stage st = make_stage(stage_base);
-    __syncthreads();  // the staging area overlays the T and cofactor tables
-#pragma unroll
-    for (int m = 0; m < kStageK; ++m) stage_put(st, lane, m, m < NMO ? float(av[m < NMO ? m : 0]) : 0.f);
-    __syncthreads();
-    mfma_apply<2, SPLIT>(S, 1, st, lane);
-    __syncthreads();
-}
-
-// Pass 2 with precomputed AO weights t (float, LDS row of this lane).
-template <typename RT>
-__device__ __forceinline__ void sigma_derivs_t(const DevSystem &S, double x0, double x1, double x2,
-                                               const float *t_row, double &g0, double &g1, double &g2,
-                                               double &lap) {
-    int p = 0, mu = 0;
-    double G0 = 0.0, G1 = 0.0, G2 = 0.0, Lp = 0.0;
-    int atom = -1;
-    RT dx = RT(0), dy = RT(0), dz = RT(0), r2 = RT(0), r = RT(0), rinv = RT(0);
-    for (int sh = 0; sh < S.n_shells; ++sh) {
-        const int4 si = S.shells[sh];
-        if (si.x != atom) {  // shells of one atom share the geometry
-            atom = si.x;
-            const double *A = S.atoms + 4 * atom;
-            dx = RT(x0 - A[0]);
-            dy = RT(x1 - A[1]);
-            dz = RT(x2 - A[2]);
-            r2 = dx * dx + dy * dy + dz * dz;
-            r = sqrt(r2);
-            rinv = RT(1) / r;
-        }
-        RT Rv, Rd, Rl;
-        shell_radial<RT, true>(S, p, si.w, si.y, si.z, r, r2, rinv, Rv, Rd, Rl);
-        p += si.w;
-        const int nc = (si.y + 1) * (si.y + 2) / 2;
-        for (int c = 0; c < nc; ++c, ++mu) {
-            const RT t = RT(t_row[mu]);
-            RT P, Px, Py, Pz, PL;
-            if (si.y == 0) {
-                P = RT(1); Px = Py = Pz = PL = RT(0);
-            } else if (si.y == 1) {
-                P = c == 0 ? dx : (c == 1 ? dy : dz);
-                Px = c == 0 ? RT(1) : RT(0);
-                Py = c == 1 ? RT(1) : RT(0);
-                Pz = c == 2 ? RT(1) : RT(0);
-                PL = RT(0);
-            } else {
-                const int iu = (c < 3) ? 0 : (c < 5 ? 1 : 2);
-                const int iv = (c == 0) ? 0 : (c == 1 || c == 3) ? 1 : 2;
-                const RT u = iu == 0 ? dx : (iu == 1 ? dy : dz);
-                const RT v = iv == 0 ? dx : (iv == 1 ? dy : dz);
-                P = u * v;
-                Px = (iu == 0 ? v : RT(0)) + (iv == 0 ? u : RT(0));
-                Py = (iu == 1 ? v : RT(0)) + (iv == 1 ? u : RT(0));
-                Pz = (iu == 2 ? v : RT(0)) + (iv == 2 ? u : RT(0));
-                PL = iu == iv ? RT(2) : RT(0);
-            }
-            const RT PRd = P * Rd;
-            G0 += double(t * (Rv * Px + PRd * dx));
-            G1 += double(t * (Rv * Py + PRd * dy));
-            G2 += double(t * (Rv * Pz + PRd * dz));
-            Lp += double(t * (Rv * PL + P * Rl));
-        }
-    }
-    g0 = G0;
-    g1 = G1;
-    g2 = G2;
-    lap = Lp;
-}
-
 // LDS of one walker (doubles): T tables [2][nmax][NMO] at 0 (nmax =
 // max(n_up, n_dn)) and the cofactor tables [2][nmax][NMO] after them, both
 // written from the determinant stage on.  Before it the same space holds
@@ -632,10 +561,13 @@ template <int NMO, bool LR>
 __host__ __device__ inline int bf_pos_offset(const DevSystem &S);
 
 // PSI: stop once log|Psi| is known (no cofactor tables, no adjoint vector):
-// the values a finite-difference kinetic energy needs.
+// the values a finite-difference kinetic energy needs.  RT is the arithmetic
+// of the AO evaluation and MF the MO contraction of pass 1 (FP64 when RT is
+// double); hi (wave-uniform) switches a mixed form to the FP64 AO/MO path.
 template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false, bool PSI = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
-                                            double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
+                                            double &x1, double &x2, Core<NMO> &c, void *stage = nullptr,
+                                            bool hi = false) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
     const int tstride = nmax * NMO;          // doubles per spin table
     double *sT = wsm;                        // [2][nmax][NMO]
@@ -681,36 +613,33 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     }
     __syncthreads();
 
-    // ---- Pade e-e Jastrow and Coulomb terms of this electron -------------
-    // The FP64 form evaluates these pair terms in FP64; the mixed forms in
-    // FP32 (RT) from displacements formed in FP64, with FP64 accumulation.
+    // ---- Pade e-e Jastrow and Coulomb terms of this electron (FP64) --------
     double J = 0.0, gJ0 = 0.0, gJ1 = 0.0, gJ2 = 0.0, lapJ = 0.0, vpot = 0.0;
     if (L.active) {
         for (int j = 0; j < S.ne; ++j) {
             if (j == L.e) continue;
             const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
-            const RT d0 = RT(x0 - sPos[3 * lj]), d1 = RT(x1 - sPos[3 * lj + 1]), d2 = RT(x2 - sPos[3 * lj + 2]);
-            const RT r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             const bool same = (j < S.n_up) == (L.e < S.n_up);
-            const RT a = RT(same ? S.a_par : S.a_anti), b = RT(S.b);
+            const double a = same ? S.a_par : S.a_anti, b = S.b;
             // one division gives both 1/r and 1/(1 + b r)
-            const RT den = RT(1) + b * r;
-            const RT q = RT(1) / (r * den);
-            const RT rinv = q * den, dinv = q * r;
-            const RT k1 = a * dinv * dinv;                    // K'(r)
-            const RT k2 = RT(-2) * a * b * dinv * dinv * dinv;  // K''(r)
-            J += double(RT(0.5) * a * r * dinv);
-            gJ0 += double(k1 * d0 * rinv);
-            gJ1 += double(k1 * d1 * rinv);
-            gJ2 += double(k1 * d2 * rinv);
-            lapJ += double(k2 + RT(2) * k1 * rinv);
-            vpot += double(RT(0.5) * rinv);
+            const double den = 1.0 + b * r;
+            const double q = 1.0 / (r * den);
+            const double rinv = q * den, dinv = q * r;
+            const double k1 = a * dinv * dinv;                // K'(r)
+            const double k2 = -2.0 * a * b * dinv * dinv * dinv;  // K''(r)
+            J += 0.5 * a * r * dinv;
+            gJ0 += k1 * d0 * rinv;
+            gJ1 += k1 * d1 * rinv;
+            gJ2 += k1 * d2 * rinv;
+            lapJ += k2 + 2.0 * k1 * rinv;
+            vpot += 0.5 * rinv;
         }
         for (int a = 0; a < S.n_atoms; ++a) {
             const double *A = S.atoms + 4 * a;
             const double d0 = x0 - A[0], d1 = x1 - A[1], d2 = x2 - A[2];
-            const RT rr = RT(d0 * d0 + d1 * d1 + d2 * d2);
-            vpot -= double(RT(A[3]) / sqrt(rr));
+            vpot -= A[3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             if (S.jas_en) {
                 // e-n kernel K = N / D, N = w0 r + w1 r^2, D = 1 + w2 r:
                 // K' = (N' - K D') / D and K'' = (N'' - 2 K' D') / D
@@ -776,7 +705,12 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
 
     // ---- pass 1: MO values of this electron ------------------------------
     double a[NMO];
-    if constexpr (MF > 0) {
+    if (sizeof(RT) == sizeof(double) || hi) {
+        double phi[NMO];
+        mo_values<NMO, double>(S, x0, x1, x2, phi);
+#pragma unroll
+        for (int m = 0; m < NMO; ++m) a[m] = phi[m];
+    } else if constexpr (MF > 0) {
         // the staging area overlays the walkers' tables: wait for the
         // position reads of the pair loop first
         __syncthreads();

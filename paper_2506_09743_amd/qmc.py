@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
-QMC_OK, QMC_EINVAL, QMC_ENOMEM, QMC_EDEVICE, QMC_EUNSUPPORTED = 0, -1, -2, -3, -4
+QMC_OK, QMC_EINVAL, QMC_ENOMEM, QMC_EDEVICE, QMC_EUNSUPPORTED, QMC_ENONFINITE = 0, -1, -2, -3, -4, -5
 QMC_FP64, QMC_MIXED_FP32, QMC_MIXED_BF16, QMC_MIXED_BF16_X1, QMC_FP64_EXPLICIT = 0, 1, 2, 3, 4
 QMC_STO, QMC_GTO = 0, 1
 PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_MIXED_FP32, "bf16": QMC_MIXED_BF16,
@@ -24,7 +24,10 @@ PRECISIONS = {"fp64": QMC_FP64, "fp32": QMC_MIXED_FP32, "bf16": QMC_MIXED_BF16,
 # every symbol include/qmc.h declares
 EXPORTS = ("qmc_system_create", "qmc_system_destroy", "qmc_eval_psi_eloc", "qmc_metropolis_block",
            "qmc_grad", "qmc_eval_eloc_fd", "qmc_param_count", "qmc_bytes_per_walker",
-           "qmc_status_string")
+           "qmc_reduce_accumulators", "qmc_status_string")
+# columns of the Metropolis accumulators [W][ACC_COLS]: sum E_L, sum E_L^2,
+# accepted steps, steps whose state had no finite log|Psi| or E_L
+ACC_COLS = 4
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -81,6 +84,8 @@ def lib():
         L.qmc_param_count.restype = C.c_int64
         L.qmc_bytes_per_walker.argtypes = [C.c_void_p, C.c_int32]
         L.qmc_bytes_per_walker.restype = C.c_size_t
+        L.qmc_reduce_accumulators.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.qmc_reduce_accumulators.restype = C.c_int
         L.qmc_status_string.argtypes = [C.c_int]
         L.qmc_status_string.restype = C.c_char_p
         _lib = L
@@ -184,7 +189,7 @@ def qmc_metropolis_block(handle, precision: int, X, logpsi, sign, eloc, n_steps:
                                       _dev_ptr(logpsi, "logpsi", (W,)), _dev_ptr(sign, "sign", (W,)),
                                       _dev_ptr(eloc, "eloc", (W,)), W, int(n_steps), float(sigma),
                                       C.c_uint64(seed), C.c_uint64(step0), C.c_uint32(walker_offset),
-                                      _dev_ptr(acc, "acc", (W, 3)), _stream()), "qmc_metropolis_block")
+                                      _dev_ptr(acc, "acc", (W, ACC_COLS)), _stream()), "qmc_metropolis_block")
 
 
 def qmc_eval_eloc_fd(handle, X, h: float, logpsi, eloc) -> None:
@@ -210,6 +215,14 @@ def qmc_param_count(handle) -> int:
 
 def qmc_bytes_per_walker(handle, precision: int = QMC_FP64) -> int:
     return int(lib().qmc_bytes_per_walker(handle, int(precision)))
+
+
+def qmc_reduce_accumulators(acc, out) -> None:
+    """out[5] (device) = column sums of acc [W][4] and the number of walkers
+    with non-finite steps, in an order fixed by W."""
+    W = acc.shape[0]
+    _check(lib().qmc_reduce_accumulators(_dev_ptr(acc, "acc", (W, ACC_COLS)), W, _dev_ptr(out, "out", (5,)),
+                                         _stream()), "qmc_reduce_accumulators")
 
 
 # ---- convenience object ------------------------------------------------------------
@@ -281,7 +294,7 @@ class System:
         import torch
         self._walkers(X)
         if acc is None:
-            acc = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
+            acc = torch.zeros((X.shape[0], ACC_COLS), dtype=torch.float64, device=X.device)
         qmc_metropolis_block(self.handle, PRECISIONS[precision], X, logpsi, sign, eloc, n_steps,
                              sigma, seed, step0, walker_offset, acc)
         return acc

@@ -18,3 +18,17 @@ def oracle_mod():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="session")
+def qmc():
+    from paper_2506_09743_amd import qmc as q
+    q.lib()
+    return q

@@ -33,8 +33,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in (0, -1, -2, -3, -4):
-        assert qmc.status_string(code)
+    for code in (0, -1, -2, -3, -4, -5):
+        assert qmc.status_string(code) != "unknown status"
     assert qmc.status_string(-99) == "unknown status"
 
 
@@ -49,13 +49,38 @@ def _bad(mutate):
     lambda d: d.__setitem__("prim_exp", -d["prim_exp"]),
     lambda d: d.__setitem__("shell_atom", d["shell_atom"] + 5),
     lambda d: d.__setitem__("occ_up", d["occ_up"] + 100),
-    lambda d: d.__setitem__("ci", d["ci"] * float("nan")),
     lambda d: d.__setitem__("normalize", 3),
-], ids=["negative b", "negative exponent", "atom index", "MO index", "NaN CI", "normalize flag"])
+], ids=["negative b", "negative exponent", "atom index", "MO index", "normalize flag"])
 def test_create_rejects_invalid_descriptor(mutate):
     with pytest.raises(qmc.QmcError) as ei:
         qmc.System(_bad(mutate))
     assert ei.value.status == qmc.QMC_EINVAL
+
+
+def _set_one(key, idx, value):
+    def mutate(d):
+        a = np.array(d[key], dtype=np.float64, copy=True)
+        a.reshape(-1)[idx] = value
+        d[key] = a
+    return mutate
+
+
+@pytest.mark.parametrize("mutate", [
+    _set_one("ci", 3, float("nan")),
+    _set_one("Z", 0, float("inf")),
+    _set_one("R", 4, float("nan")),
+    _set_one("prim_exp", 2, float("inf")),
+    _set_one("prim_coef", 1, float("nan")),
+    _set_one("mo_coef", 7, float("-inf")),
+    lambda d: d.__setitem__("jas_b", float("nan")),
+    lambda d: d.__setitem__("jas_a_anti", float("inf")),
+], ids=["CI", "Z", "R", "exponent", "contraction", "MO coefficient", "Pade b", "Pade a"])
+def test_create_reports_non_finite_descriptor_values(mutate):
+    """A NaN or infinite descriptor value is QMC_ENONFINITE, before any
+    device is touched."""
+    with pytest.raises(qmc.QmcError) as ei:
+        qmc.System(_bad(mutate))
+    assert ei.value.status == qmc.QMC_ENONFINITE
 
 
 def test_create_rejects_unsupported_shapes():
@@ -80,6 +105,8 @@ def test_null_arguments_rejected():
     assert L.qmc_eval_eloc_fd(None, None, 1, 1e-3, None, None, None) == qmc.QMC_EINVAL
     assert L.qmc_param_count(None) == -1
     assert L.qmc_bytes_per_walker(None, 0) == 0
+    assert L.qmc_reduce_accumulators(None, 4, None, None) == qmc.QMC_EINVAL
+    assert L.qmc_reduce_accumulators(None, -1, None, None) == qmc.QMC_EINVAL
     L.qmc_system_destroy(None)
 
 
@@ -105,16 +132,17 @@ def _mbj_bad(mutate):
 
 
 @pytest.mark.parametrize("mutate", [
-    lambda d: d["jas_en"].__setitem__((0, 2), -1.0),
-    lambda d: d["jas_en"].__setitem__((1, 0), float("inf")),
-    lambda d: d["jas_een"].__setitem__((0, 4), -0.5),
-    lambda d: d["jas_een"].__setitem__((2, 0), float("nan")),
-    lambda d: d.__setitem__("jas_een", np.ones((9, 7))),
+    (lambda d: d["jas_en"].__setitem__((0, 2), -1.0), qmc.QMC_EINVAL),
+    (lambda d: d["jas_en"].__setitem__((1, 0), float("inf")), qmc.QMC_ENONFINITE),
+    (lambda d: d["jas_een"].__setitem__((0, 4), -0.5), qmc.QMC_EINVAL),
+    (lambda d: d["jas_een"].__setitem__((2, 0), float("nan")), qmc.QMC_ENONFINITE),
+    (lambda d: d.__setitem__("jas_een", np.ones((9, 7))), qmc.QMC_EINVAL),
 ], ids=["e-n w2 < 0", "e-n infinite", "e-e-n b < 0", "e-e-n NaN", "more than 8 terms"])
 def test_create_rejects_invalid_many_body_terms(mutate):
+    mutate, status = mutate
     with pytest.raises(qmc.QmcError) as ei:
         qmc.System(_mbj_bad(mutate))
-    assert ei.value.status == qmc.QMC_EINVAL
+    assert ei.value.status == status
 
 
 def test_valid_many_body_terms_pass_validation():
@@ -136,7 +164,7 @@ def test_create_rejects_non_finite_backflow(omega):
     d["bf_omega"] = omega
     with pytest.raises(qmc.QmcError) as ei:
         qmc.System(d)
-    assert ei.value.status == qmc.QMC_EINVAL
+    assert ei.value.status == qmc.QMC_ENONFINITE
 
 
 def test_valid_backflow_passes_validation():

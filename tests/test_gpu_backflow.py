@@ -204,7 +204,7 @@ def test_backflow_block_equals_single_steps(torch_cuda, oracle_mod, name, W, pre
     a = state()
     acc_a = s.metropolis(*a, steps, sigma, seed, step0=step0, precision=prec)
     b = state()
-    acc_b = torch.zeros((W, 3), dtype=torch.float64, device="cuda")
+    acc_b = torch.zeros((W, 4), dtype=torch.float64, device="cuda")
     for t in range(steps):
         s.metropolis(*b, 1, sigma, seed, step0=step0 + t, acc=acc_b, precision=prec)
     torch.cuda.synchronize()

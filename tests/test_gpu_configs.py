@@ -34,7 +34,7 @@ def _run_gpu(torch, sysd, W, n_steps, chunk):
     X = torch.from_numpy(X0.copy()).cuda()
     lp, sg, el = s.eval(X)
     lp0, sg0, el0 = [t.cpu().numpy() for t in (lp, sg, el)]
-    acc = torch.zeros((W, 3), dtype=torch.float64, device="cuda")
+    acc = torch.zeros((W, 4), dtype=torch.float64, device="cuda")
     for s0 in range(0, n_steps, chunk):
         s.metropolis(X, lp, sg, el, min(chunk, n_steps - s0), synth.CONFIG_SIGMA, synth.PHILOX_SEED[name],
                      step0=s0, acc=acc)

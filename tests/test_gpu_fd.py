@@ -88,10 +88,11 @@ def test_fd_rejects(torch_cuda):
     sysd = synth.make_system("LiH")
     s = qmc.System(sysd)
     X = torch.from_numpy(synth.init_walkers(sysd, 4, 1)).cuda()
-    for h in (0.0, -1e-3, float("nan")):
+    for h, status in ((0.0, qmc.QMC_EINVAL), (-1e-3, qmc.QMC_EINVAL), (float("nan"), qmc.QMC_ENONFINITE),
+                      (float("inf"), qmc.QMC_ENONFINITE)):
         with pytest.raises(qmc.QmcError) as e:
             s.eval_fd(X, h)
-        assert e.value.status == qmc.QMC_EINVAL
+        assert e.value.status == status
     s.close()
     bf = dict(sysd)
     bf["bf_omega"] = 0.2

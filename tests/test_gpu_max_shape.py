@@ -153,7 +153,7 @@ def test_max_shape_backflow_metropolis(torch_cuda, oracle_mod, precision):
     blk = state(X, lp, sg, el)
     acc_blk = s.metropolis(*blk, 3, sigma, seed, step0=0, precision=precision)
     one = state(X, lp, sg, el)
-    acc_one = torch.zeros((W, 3), dtype=torch.float64, device="cuda")
+    acc_one = torch.zeros((W, 4), dtype=torch.float64, device="cuda")
     for t in range(3):
         s.metropolis(*one, 1, sigma, seed, step0=t, acc=acc_one, precision=precision)
     torch.cuda.synchronize()

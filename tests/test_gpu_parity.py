@@ -237,6 +237,10 @@ def test_abi_rejects_bad_arguments(torch_cuda, qmc):
     assert L.qmc_metropolis_block(s.handle, 0, C.c_void_p(X.data_ptr()), p, p, p, 4, -1, 0.2, 1, 0, 0,
                                   p, None) == qmc.QMC_EINVAL
     assert L.qmc_metropolis_block(s.handle, 0, C.c_void_p(X.data_ptr()), p, p, p, 4, 1, float("nan"),
+                                  1, 0, 0, p, None) == qmc.QMC_ENONFINITE
+    assert L.qmc_metropolis_block(s.handle, 0, C.c_void_p(X.data_ptr()), p, p, p, 4, 1, float("inf"),
+                                  1, 0, 0, p, None) == qmc.QMC_ENONFINITE
+    assert L.qmc_metropolis_block(s.handle, 0, C.c_void_p(X.data_ptr()), p, p, p, 4, 1, -0.1,
                                   1, 0, 0, p, None) == qmc.QMC_EINVAL
     assert L.qmc_metropolis_block(s.handle, 0, C.c_void_p(X.data_ptr()), p, p, p, 4, 1, 0.2, 1, 0,
                                   0xFFFFFFFE, p, None) == qmc.QMC_EINVAL
@@ -248,10 +252,9 @@ def test_abi_rejects_bad_arguments(torch_cuda, qmc):
                                                ("LiH", "bf16", 1e-3), ("CO", "bf16", 1e-3),
                                                ("CO", "bf16x1", 1e-1)])
 def test_mixed_error(torch_cuda, qmc, oracle_mod, name, prec, med_tol):
-    """Mixed forms (FP32 AOs; MO contractions in FP32 or on BF16 matrix
-    cores; FP64 elsewhere): per-walker E_L error and mean-energy error
-    against the oracle, reported and bounded loosely (a precision study,
-    not an FP64 parity check)."""
+    """Mixed forms (FP32 AOs; MO value contraction in FP32 or on BF16 matrix
+    cores; FP64 elsewhere) on raw initial walkers: per-walker relative E_L
+    error against the oracle (median bounded), and the sign of Psi."""
     torch = torch_cuda
     sysd = synth.make_system(name)
     X = synth.init_walkers(sysd, 512, 12)
@@ -264,6 +267,58 @@ def test_mixed_error(torch_cuda, qmc, oracle_mod, name, prec, med_tol):
           f"mean-energy err {abs(el.mean() - rel.mean()):.2e}")
     assert np.median(rel_err) < med_tol
     assert np.mean(sg == rsg) > (0.99 if prec != "bf16x1" else 0.8)
+
+
+_CO_EQ = {}
+
+
+def _co_equilibrated(torch, qmc):
+    """The CO workload's 65536 walkers after 500 FP64 Metropolis steps (the
+    benchmark's burn-in), and their FP64 log|Psi|, E_L."""
+    if not _CO_EQ:
+        sysd = synth.make_system("CO")
+        s = _gpu_system(qmc, "CO")
+        X = torch.from_numpy(synth.init_walkers(sysd, synth.CONFIG_WALKERS["CO"], synth.WALKER_SEED["CO"])).cuda()
+        lp, sg, el = s.eval(X)
+        for k in range(50):
+            s.metropolis(X, lp, sg, el, 10, synth.CONFIG_SIGMA, synth.PHILOX_SEED["CO"], step0=10 * k)
+        _CO_EQ.update(X=X, lp=lp, el=el, sysd=sysd, s=s)
+    return _CO_EQ
+
+
+MEAN_E_TOL = 1e-4  # Ha: the workload's bar for the mixed form's mean-energy error
+
+
+@pytest.mark.parametrize("prec", [
+    "fp32",
+    pytest.param("bf16", marks=pytest.mark.xfail(
+        strict=True, reason="16-bit split BF16 MO values: the mean-energy error is ~1e-3 Ha, "
+                            "above the 1e-4 Ha bar (a stated error, not a claim)")),
+])
+def test_mixed_mean_energy_error_co_64k(torch_cuda, qmc, oracle_mod, prec):
+    """Mean-energy error of a mixed form on identical configurations (the
+    FP64 chain's equilibrated CO walkers re-evaluated): over all 65536
+    walkers against the FP64 form, and on a 4096-walker sample against the
+    oracle; both within 1e-4 Ha."""
+    torch = torch_cuda
+    eq = _co_equilibrated(torch, qmc)
+    s, X = eq["s"], eq["X"]
+    lp_m, _, el_m = [t.cpu().numpy() for t in s.eval(X, precision=prec)]
+    el64 = eq["el"].cpu().numpy()
+    ok = np.isfinite(el64)
+    assert np.array_equal(ok, np.isfinite(el_m))
+    d_all = el_m[ok].mean() - el64[ok].mean()
+    idx = np.random.default_rng(1).choice(X.shape[0], size=4096, replace=False)
+    idx = idx[ok[idx]]
+    Xn = X.cpu().numpy()[idx]
+    _, _, rel = oracle_mod.OracleSystem(eq["sysd"]).eval(Xn)
+    d_or = el_m[idx].mean() - rel.mean()
+    exact = np.mean(el_m[ok] == el64[ok])
+    print(f"CO 64k {prec}: mean E_L {el64[ok].mean():.6f} Ha; mixed - FP64 over all walkers {d_all:.2e}, "
+          f"mixed - oracle on 4096 {d_or:.2e}; median |dE_L| {np.median(np.abs(el_m[ok] - el64[ok])):.2e}, "
+          f"walkers equal to FP64 (refined) {exact:.4%}")
+    assert abs(d_all) <= MEAN_E_TOL
+    assert abs(d_or) <= MEAN_E_TOL
 
 
 def test_mixed_bf16_metropolis_runs(torch_cuda, qmc):

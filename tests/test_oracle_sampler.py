@@ -137,3 +137,41 @@ def test_metropolis_resume_bitwise(oracle_mod):
     b2 = o.metropolis(*b1[:4], 12, 0.2, 5, step0=8, acc=b1[4])
     for u, v in zip(a[:5], b2[:5]):
         assert np.array_equal(u, v)
+
+
+def test_metropolis_counts_non_finite_states(oracle_mod):
+    """The Monte Carlo mean of eq. Ev runs over states with a finite E_L: a
+    state without a finite log|Psi| or E_L (NaN positions, or two same-spin
+    electrons at one point, where every determinant vanishes) adds to the
+    fourth accumulator column and to neither sum.  A finite walker's sums
+    are the plain sums of its post-decision E_L over the steps."""
+    sysd = synth.make_system("LiH")
+    o = oracle_mod.OracleSystem(sysd)
+    X = synth.init_walkers(sysd, 3, 5)
+    X[1] = np.nan
+    X[2, 1] = X[2, 0]  # spin-up electrons 0 and 1 coincide
+    lp, sg, el = o.eval(X)
+    assert np.isfinite(el[0]) and not np.isfinite(lp[1]) and lp[2] == -np.inf
+    steps = 6
+    # sigma = 0: every proposal is the current state, so nothing can recover
+    _, _, _, _, acc0, _ = o.metropolis(X, lp, sg, el, steps, 0.0, 11)
+    assert acc0[0, 3] == 0 and acc0[1, 3] == steps and acc0[2, 3] == steps
+    assert acc0[1, 0] == 0 and acc0[1, 1] == 0 and acc0[2, 0] == 0
+    assert acc0[1, 2] == 0 and acc0[2, 2] == 0
+    # sigma > 0: the coincident walker's first proposal separates the
+    # electrons and is always accepted (|Psi| = 0 before it); the NaN walker
+    # never moves
+    Xs, lps, _, els, acc, _ = o.metropolis(X, lp, sg, el, steps, 0.2, 11)
+    assert acc[1, 3] == steps and acc[1, 2] == 0 and np.all(np.isnan(Xs[1]))
+    assert acc[2, 3] == 0 and acc[2, 2] >= 1 and np.isfinite(acc[2, 0])
+    # the finite walker: its sums replayed one step at a time
+    state = [X[:1], lp[:1], sg[:1], el[:1]]
+    s1 = s2 = 0.0
+    for t in range(steps):
+        Xn, lpn, sgn, eln, _, _ = o.metropolis(*state, 1, 0.2, 11, step0=t)
+        state = [Xn, lpn, sgn, eln]
+        s1 += eln[0]
+        s2 += eln[0] * eln[0]
+    assert acc[0, 3] == 0
+    assert abs(acc[0, 0] - s1) <= 1e-12 * max(1.0, abs(s1))
+    assert abs(acc[0, 1] - s2) <= 1e-12 * max(1.0, abs(s2))

@@ -1,5 +1,7 @@
-"""Serving host logic that needs no GPU: footprint admission refusal, the
-fixed-order accumulator reduction and the request stream recipe."""
+"""Serving host logic that needs no GPU: the block statistics from the
+device's accumulator sums and the request stream recipe.  (Footprints come
+from qmc_bytes_per_walker, which needs a device handle: the admission tests
+run on the GPU.)"""
 import math
 
 import numpy as np
@@ -8,26 +10,32 @@ import pytest
 from paper_2506_09743_amd import serve, synth
 
 
-def test_oversize_request_is_refused():
-    s = serve.Server(hbm_budget_bytes=1 << 20)
-    fut = s.submit(serve.Request(id=1, name="CO", bond_scale=1.0, walkers=4096, steps=10))
-    with pytest.raises(serve.AdmissionError):
-        fut.result(timeout=1)
-
-
-def test_footprint_matches_walker_state():
-    req = serve.Request(id=1, name="LiH", bond_scale=1.3, walkers=1000, steps=10)
-    assert serve.Server.footprint(req) == 1000 * (3 * 4 + 6) * 8 + (1 << 20)
-
-
-def test_reduce_accumulators_fixed_order():
+def test_block_statistics_from_device_sums():
+    """Mean, variance and acceptance from the five sums of
+    qmc_reduce_accumulators; non-finite walker-steps leave the mean."""
     rng = np.random.default_rng(0)
-    acc = np.c_[rng.standard_normal(1000) * 1e6, rng.random(1000) * 1e12, rng.integers(0, 5, 1000)]
-    m1 = serve.reduce_accumulators(acc, 5)
-    m2 = serve.reduce_accumulators(acc.copy(), 5)
-    assert m1 == m2
-    assert math.isclose(m1[0], acc[:, 0].sum() / 5000, rel_tol=1e-12)
-    assert math.isclose(m1[2], acc[:, 2].sum() / 5000)
+    W, steps = 1000, 5
+    e = rng.standard_normal((W, steps)) * 3.0 - 10.0
+    acc = np.c_[e.sum(1), (e * e).sum(1), rng.integers(0, 6, W), np.zeros(W)]
+    sums = [acc[:, 0].sum(), acc[:, 1].sum(), acc[:, 2].sum(), 0.0, 0.0]
+    mean, var, accr, bad, bad_w = serve.block_statistics(sums, W, steps)
+    assert math.isclose(mean, e.mean(), rel_tol=1e-12)
+    assert math.isclose(var, e.var(), rel_tol=1e-9)
+    assert math.isclose(accr, acc[:, 2].sum() / (W * steps))
+    assert (bad, bad_w) == (0, 0)
+    # two walkers with 3 and 5 non-finite steps: their sums hold only the finite steps
+    e2 = e.copy()
+    e2[7, :3] = np.nan
+    e2[9, :] = np.nan
+    fin = np.isfinite(e2)
+    s = [np.where(fin, e2, 0).sum(), np.where(fin, e2 * e2, 0).sum(), 0.0, float((~fin).sum()), 2.0]
+    mean2, var2, _, bad2, bad_w2 = serve.block_statistics(s, W, steps)
+    assert (bad2, bad_w2) == (8, 2)
+    assert math.isclose(mean2, e2[fin].mean(), rel_tol=1e-12)
+    assert math.isclose(var2, e2[fin].var(), rel_tol=1e-9)
+    # nothing finite: the mean is undefined, not a division by zero
+    m3 = serve.block_statistics([0.0, 0.0, 0.0, float(W * steps), float(W)], W, steps)
+    assert math.isnan(m3[0]) and m3[3] == W * steps
 
 
 def test_request_stream_recipe():
