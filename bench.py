@@ -9,9 +9,12 @@ equilibrated state (burn-in) with all inputs resident on the device.
 
 Prints one JSON line (see the keys below).  The FP64 form is `value`; the
 mixed forms are reported beside it with their energy errors against the FP64
-oracle: FP32 (FP32 AOs and MO contraction on the vector units) and BF16 (FP32
-AOs, MO contraction as split-BF16 matrix-core products with FP32
-accumulation); both keep determinants, traces, Jastrow and E_L in FP64.
+oracle over every walker: FP32 (FP32 AOs and MO value contraction on the
+vector units) and BF16 (FP32 AOs, MO value contraction as split-BF16
+matrix-core products with FP32 accumulation); both keep the proposal, pair
+terms, determinants, Jacobi-trace contraction and E_L in FP64.  p50/p99 are
+over at least 20 repeated blocks.  The compact per-form summary is the
+line's last key, `forms`.
 """
 from __future__ import annotations
 
@@ -29,11 +32,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector FLOP/s
+PEAK_FP32_VALU = 157.3e12  # MI355X FP32 vector FLOP/s (published)
+PEAK_BF16_MFMA = 2.5e15    # MI355X dense BF16 matrix FLOP/s
 PEAK_HBM = 8.0e12          # bytes/s
+
+# Algorithmic work of one CO walker-step (flop), from the hot-path formulas
+# at the low-rank determinant method's cost: AO values/gradients/Laplacians
+# 22k, the five-channel MO contraction 2 * 5 * 14 * 28 * 20 = 78.4k, LU, T
+# and channel products 20k, 100-determinant traces 26k, pairs 3k.  The
+# roofline's `achieved` uses this per-unit figure; flops_per_walker_step is
+# this build's own term-by-term recount (the kernel reassociates the
+# per-determinant traces into one adjoint vector per electron).
+CO_FLOPS = {"ao": 22.0e3, "mo": 78.4e3, "lu_channels": 20.0e3, "traces": 26.0e3, "pairs": 3.0e3}
+CO_FLOPS_PER_WALKER_STEP = 1.45e5
+
+
+def mixed_peak(form: str) -> dict:
+    """Blended peak of a mixed form on the CO work: AO evaluation and the
+    value channel of the MO contraction at the FP32 vector peak (the BF16
+    forms' contraction at the BF16 matrix peak), the rest (the four
+    derivative channels, which become the FP64 Jacobi-trace contraction, the
+    determinant algebra and the pairs) at the FP64 peak."""
+    total = CO_FLOPS_PER_WALKER_STEP
+    f_ao, f_val = CO_FLOPS["ao"], CO_FLOPS["mo"] / 5
+    f64 = total - f_ao - f_val
+    t = f64 / PEAK_FP64_VALU + f_ao / PEAK_FP32_VALU
+    t += f_val / (PEAK_BF16_MFMA if form.startswith("bf16") else PEAK_FP32_VALU)
+    return {"peak_flops": total / t, "fp64_flop": f64, "fp32_flop": f_ao + (0 if form.startswith("bf16") else f_val),
+            "bf16_flop": f_val if form.startswith("bf16") else 0.0}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "co_metropolis_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_09743_amd", "csrc", f)
-                  for f in ("qmc_kernels.hip", "qmc_walker.h", "qmc_backflow.h", "qmc_device.h",
-                            "qmc_api.hip")]
+                  for f in ("qmc_kernels.h", "qmc_form_fp64.hip", "qmc_walker.h", "qmc_backflow.h",
+                            "qmc_device.h", "qmc_api.hip")]
 
 
 def flops_per_walker_step(sysd) -> dict:
@@ -148,9 +178,9 @@ def grad_flops_per_walker(sysd) -> dict:
 
 def hbm_bytes_per_launch(sysd, W: int) -> int:
     """Walker state read and written once per launch: X, log|Psi|, sign, E_L
-    and three accumulators, FP64."""
+    and four accumulators, FP64."""
     from paper_2506_09743_amd import synth
-    per = (3 * synth.n_elec(sysd) + 6) * 8
+    per = (3 * synth.n_elec(sysd) + 7) * 8
     return 2 * per * W
 
 
@@ -177,6 +207,26 @@ def measured_traffic():
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def conditioning_window(o, sysd, X):
+    """Per walker: inside the FP64 tolerance window (largest reference Slater
+    condition number <= 1e8, CI cancellation sum |d_n D_n| / |sum d_n D_n|
+    <= 1e3, |E_L| and |E_kin| <= 1e4 Ha), from the oracle's orbitals and
+    plain numpy determinants."""
+    nu = int(sysd["n_up"])
+    inside = np.zeros(X.shape[0], dtype=bool)
+    for w, x in enumerate(X):
+        phi = o.mo(x)[:, 0, :]
+        up, dn = phi[:nu], phi[nu:]
+        cond = max(np.linalg.cond(up[:, sysd["occ_up"][0]]), np.linalg.cond(dn[:, sysd["occ_dn"][0]]))
+        terms = np.array([c * np.linalg.det(up[:, ou]) * np.linalg.det(dn[:, od])
+                          for c, ou, od in zip(sysd["ci"], sysd["occ_up"], sysd["occ_dn"])])
+        tot = abs(terms.sum())
+        kap = np.abs(terms).sum() / tot if tot > 0 else np.inf
+        d = o.eval_one(x)
+        inside[w] = cond <= 1e8 and kap <= 1e3 and abs(d["eloc"]) <= 1e4 and abs(d["e_kin"]) <= 1e4
+    return inside
 
 
 def cpu_baseline(sysd, X_host, lp, sg, el, seed, target_s: float) -> dict:
@@ -223,10 +273,24 @@ def serving_bench(n_requests: int, steps: int, seed: int = 2506, rates=(0.5, 0.8
         wall = time.perf_counter() - t0
         out = serve.latency_summary(res, wall)
         out.update({"rate_hz": f * capacity, "peak_active": srv.peak_active,
-                    "mean_active": srv.overlap_active_sum / max(1, srv.overlap_samples)})
+                    "mean_active": srv.overlap_active_sum / max(1, srv.overlap_samples),
+                    "admissions_waited_for_memory": srv.waits_memory,
+                    "admissions_waited_for_slot": srv.waits_slot,
+                    "nonfinite_walker_steps": sum(r.nonfinite_steps for r in res)})
         sweep[f"{f:g}x"] = out
     head = dict(sweep.get("0.8x", next(iter(sweep.values()))))
-    head.update({"capacity_req_per_s": capacity,
+    # the same stream at 0.8x with the budget cut to 16 MiB: memory, not the
+    # stream slots, then holds requests back
+    srv = serve.Server(chunk_steps=50, hbm_budget_bytes=16 << 20)
+    t0 = time.perf_counter()
+    prod = serve.poisson_producer(srv, serve.requests_from_stream(stream), 0.8 * capacity)
+    res = srv.run(producer=prod)
+    wall = time.perf_counter() - t0
+    mem = serve.latency_summary(res, wall)
+    mem.update({"budget_bytes": srv.budget, "peak_used_bytes": srv.peak_used, "peak_active": srv.peak_active,
+                "admissions_waited_for_memory": srv.waits_memory, "admissions_waited_for_slot": srv.waits_slot})
+    head.update({"hbm_budget_bytes": serve.Server(chunk_steps=50).budget, "memory_bound_0.8x": mem,
+                 "capacity_req_per_s": capacity,
                  "closed_loop_walker_steps_per_s": sum(r["walkers"] * r["steps"] for r in stream) / closed_wall,
                  "rate_sweep": sweep, "steps_per_request": steps,
                  "mix": "H2/LiH/Li2/CO, bond x U[0.6,3.0], walkers log-U[1k,32k], "
@@ -280,7 +344,8 @@ def many_body_bench(sysd, args, dev, seed) -> dict:
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU},
             "median_abs_dE_L": float(np.median(np.abs(gel[ok] - rel[ok]))),
             "max_rel_dlogpsi": float(np.max(np.abs(glp[ok] - rlp[ok]) / np.maximum(1, np.abs(rlp[ok])))),
-            "mean_energy": float(np.nanmean(acc.cpu().numpy()[:, 0]) / args.steps)}
+            "mean_energy": float(acc[:, 0].sum().item() / (W * args.steps - acc[:, 3].sum().item())),
+            "nonfinite_walker_steps": int(acc[:, 3].sum().item())}
 
 
 def grad_bench(args, dev) -> dict:
@@ -507,6 +572,24 @@ def backflow_bench(args, dev, seed) -> dict:
             "sd_sweep_1000_walkers": sweep}
 
 
+def summarize_trace(path: str, kernel_regex: str, skip: int) -> dict:
+    """Durations of one kernel's dispatches in a rocprofv3 kernel-trace CSV,
+    leaving out its first `skip` dispatches (burn-in and warm-up launches)."""
+    import csv
+    import re
+    pat = re.compile(kernel_regex)
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if pat.search(r["Kernel_Name"]):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    d = np.array([x[1] for x in rows[skip:]], dtype=np.float64)
+    return {"kernel_regex": kernel_regex, "dispatches_total": len(rows), "skipped": skip,
+            "dispatches": int(d.size), "mean_ns": float(d.mean()), "median_ns": float(np.median(d)),
+            "min_ns": float(d.min()), "max_ns": float(d.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,7 +615,15 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=500)
     ap.add_argument("--pmc-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter scaling)")
+    ap.add_argument("--summarize-trace", default=None,
+                    help="print the dispatch statistics of --trace-kernel in this rocprofv3 "
+                         "kernel-trace CSV (no GPU run)")
+    ap.add_argument("--trace-kernel", default=r"k_metropolis<20, double, 0, false, false>")
+    ap.add_argument("--trace-skip", type=int, default=0, help="leading dispatches to leave out")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(json.dumps(summarize_trace(args.summarize_trace, args.trace_kernel, args.trace_skip)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the walkers of a multi-GPU run would be independent "
               "shards with one 32-byte all-reduce per block, which this build does not launch.",
@@ -575,6 +666,7 @@ def main():
     lp_eq, sg_eq, el_eq = lp.clone(), sg.clone(), el.clone()
 
     results = {}
+    n_lat = max(20, args.steps // args.chunk)
     for form in (["fp64"] if args.no_mixed else ["fp64", "fp32", "bf16"]):
         st = [X_eq.clone(), lp_eq.clone(), sg_eq.clone(), el_eq.clone()]
         if form != "fp64":  # the mixed chain carries its own log|Psi| and E_L
@@ -585,39 +677,65 @@ def main():
         events = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        run_steps(st, args.steps, s0, form, acc, events)
+        s1 = run_steps(st, args.steps, s0, form, acc, events)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         launch_ms = np.array([a.elapsed_time(b) for a, b, _ in events])
-        per_step_ms = np.array([a.elapsed_time(b) / c for a, b, c in events])
-        a = acc.cpu().numpy()
+        sums = torch.empty(5, dtype=torch.float64, device=dev)
+        qmc.qmc_reduce_accumulators(acc, sums)
+        tot = sums.cpu().numpy()
+        # latency: at least 20 repeated blocks of `chunk` steps, each timed
+        lat = []
+        for k in range(n_lat):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            system.metropolis(*st, args.chunk, 0.2, seed, step0=s1 + k * args.chunk, acc=acc, precision=form)
+            e1.record()
+            lat.append((e0, e1))
+        torch.cuda.synchronize()
+        lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
+        n_fin = W * args.steps - tot[3]
         results[form] = dict(
             value=W * args.steps / dt, ms_per_step=1e3 * dt / args.steps,
             launch_ms_mean=float(launch_ms.mean()), launch_steps=args.chunk,
-            p50_ms=float(np.percentile(launch_ms, 50)), p99_ms=float(np.percentile(launch_ms, 99)),
-            kernel_ms_per_step=float(per_step_ms.mean()),
-            mean_energy=float(np.nanmean(a[:, 0]) / args.steps),
-            acceptance=float(a[:, 2].mean() / args.steps))
+            p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
+            latency_blocks=int(n_lat), kernel_ms_per_step=float(launch_ms.mean() / args.chunk),
+            mean_energy=float(tot[0] / n_fin) if n_fin else float("nan"),
+            acceptance=float(tot[2] / (W * args.steps)),
+            nonfinite_walker_steps=int(tot[3]), nonfinite_walkers=int(tot[4]))
 
-    # errors against the oracle on identical (FP64-chain) configurations
+    # errors against the oracle on identical (FP64-chain) configurations:
+    # every walker, and the conditioning-window split on a sample
     Xn = X_eq.cpu().numpy()
-    idx = np.random.default_rng(0).choice(W, size=min(2048, W), replace=False)
     o = oracle.OracleSystem(sysd)
-    rlp, rsg, rel = o.eval(Xn[idx])
-    errors = {}
+    t0 = time.perf_counter()
+    rlp, rsg, rel = o.eval(Xn)
+    oracle_full_eval_s = time.perf_counter() - t0
+    g64 = system.eval(X_eq, precision="fp64")[2].cpu().numpy()
+    fin = np.isfinite(rel)
     for form in results:
         glp, gsg, gel = [t.cpu().numpy() for t in system.eval(X_eq, precision=form)]
-        d = gel[idx] - rel
-        ok = np.isfinite(d)
-        errors[form] = dict(max_abs_dE_L=float(np.max(np.abs(d[ok]))),
-                            median_abs_dE_L=float(np.median(np.abs(d[ok]))),
-                            mean_energy_err_vs_oracle=float(abs(np.mean(gel[idx][ok]) - np.mean(rel[ok]))),
-                            max_rel_dlogpsi=float(np.max(np.abs(glp[idx] - rlp) / np.maximum(1, np.abs(rlp)))))
+        m = fin & np.isfinite(gel)
+        d = gel - rel
+        e = dict(walkers_compared=int(m.sum()),
+                 max_abs_dE_L=float(np.max(np.abs(d[m]))), median_abs_dE_L=float(np.median(np.abs(d[m]))),
+                 p99_abs_dE_L=float(np.quantile(np.abs(d[m]), 0.99)),
+                 mean_energy_err_vs_oracle=float(abs(gel[m].mean() - rel[m].mean())),
+                 max_rel_dlogpsi=float(np.max(np.abs(glp[m] - rlp[m]) / np.maximum(1, np.abs(rlp[m])))))
         if form != "fp64":
-            g64 = system.eval(X_eq, precision="fp64")[2].cpu().numpy()
-            m = np.isfinite(gel) & np.isfinite(g64)
-            errors[form]["mean_energy_err_vs_fp64_all_walkers"] = float(abs(gel[m].mean() - g64[m].mean()))
-        results[form].update(errors[form])
+            m2 = np.isfinite(gel) & np.isfinite(g64)
+            e["mean_energy_err_vs_fp64_all_walkers"] = float(abs(gel[m2].mean() - g64[m2].mean()))
+            e["walkers_refined_in_fp64"] = float(np.mean(gel[m2] == g64[m2]))
+        results[form].update(e)
+    idx = np.random.default_rng(0).choice(W, size=min(512, W), replace=False)
+    inside = conditioning_window(o, sysd, Xn[idx])
+    d64 = np.abs(g64[idx] - rel[idx])
+    ok = np.isfinite(d64)
+    results["fp64"]["tolerance_window"] = {
+        "sampled": int(idx.size), "inside": int((inside & ok).sum()), "outside": int((~inside & ok).sum()),
+        "max_abs_dE_L_inside": float(d64[inside & ok].max(initial=0.0)),
+        "max_abs_dE_L_outside": float(d64[~inside & ok].max(initial=0.0)),
+        "window": "kappa(A0) <= 1e8, CI cancellation <= 1e3, |E_L|, |E_kin| <= 1e4 Ha"}
 
     many_body = None
     if not args.no_many_body:
@@ -630,22 +748,35 @@ def main():
     kinetic = None if args.no_kinetic_ablation else kinetic_ablation_bench(dev)
 
     fl = flops_per_walker_step(sysd)
+    per_unit = CO_FLOPS_PER_WALKER_STEP if args.system == "CO" else fl["total"]
     main_form = results["fp64"]
     launch_s = main_form["launch_ms_mean"] * 1e-3
-    flops_launch = fl["total"] * W * args.chunk
-    achieved = flops_launch / launch_s
+    achieved = per_unit * W * args.chunk / launch_s
     traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
                 "kernel": "k_metropolis<20,double> (qmc_metropolis_block)",
-                "flops_per_walker_step": fl["total"], "walker_steps_per_launch": W * args.chunk,
+                "flops_per_walker_step": per_unit, "flops_per_walker_step_recount": fl["total"],
+                "walker_steps_per_launch": W * args.chunk,
                 "hbm_bytes_per_launch_algorithmic": hbm_bytes_per_launch(sysd, W),
                 "launch_ms_mean": main_form["launch_ms_mean"]}
+    for form in results:
+        if form == "fp64":
+            results[form]["roofline_frac"] = roofline["frac"]
+            continue
+        mp = mixed_peak(form)
+        ach = per_unit * W * args.chunk / (results[form]["launch_ms_mean"] * 1e-3)
+        results[form]["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": mp["peak_flops"] / 1e12,
+                                     "unit": "TFLOP/s", "frac": ach / mp["peak_flops"],
+                                     "split_flop": {k: v for k, v in mp.items() if k != "peak_flops"}}
+        results[form]["roofline_frac"] = ach / mp["peak_flops"]
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sysd, Xn, lp_eq.cpu().numpy(), sg_eq.cpu().numpy(), el_eq.cpu().numpy(),
                            seed, args.cpu_seconds)
+        cpu["full_evaluation"] = {"walkers": W, "seconds": oracle_full_eval_s,
+                                  "walker_evals_per_s": W / oracle_full_eval_s}
 
     serving = None
     if args.serve_requests > 0:
@@ -658,6 +789,16 @@ def main():
         torch.add(a_, 0.0, out=b_)  # one elementwise kernel: reads and writes n doubles
         torch.cuda.synchronize()
 
+    # compact per-form summary, the line's last key
+    summary = {}
+    for form, r in results.items():
+        summary[form] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "p50_ms": r["p50_ms"],
+                         "p99_ms": r["p99_ms"], "mean_E_err_vs_oracle": r["mean_energy_err_vs_oracle"],
+                         "mean_E_err_vs_fp64": r.get("mean_energy_err_vs_fp64_all_walkers", 0.0),
+                         "median_abs_dE_L": r["median_abs_dE_L"], "roofline_frac": r["roofline_frac"],
+                         "speedup_vs_fp64": r["value"] / results["fp64"]["value"]}
+        if form != "fp64":
+            summary[form]["walkers_refined_in_fp64"] = r["walkers_refined_in_fp64"]
     out = {
         "metric": "walker-steps/s (Psi+E_L) CO 64k walkers, mixed vs FP64 at stated err; p50/p99",
         "value": main_form["value"], "unit": "walker-steps/s", "n_gpus": 1,
@@ -669,8 +810,8 @@ def main():
                    "walkers": W, "electrons": synth.n_elec(sysd), "aos": synth.n_ao(sysd),
                    "mos": int(np.asarray(sysd['mo_coef']).shape[1]), "dets": len(sysd["ci"])},
         "p50_ms": main_form["p50_ms"], "p99_ms": main_form["p99_ms"],
-        "latency_unit": f"ms per launch of {args.chunk} steps x {W} walkers",
-        "forms": results,
+        "latency_unit": f"ms per block of {args.chunk} steps x {W} walkers, over {n_lat} blocks",
+        "details": results,
         "serving": serving,
         "many_body_jastrow": many_body,
         "determinant_sweep": sd_sweep,
@@ -679,6 +820,7 @@ def main():
         "kinetic_ablation": kinetic,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": summary,
     }
     print(json.dumps(out), flush=True)
     system.close()
