@@ -25,6 +25,7 @@
 #pragma once
 
 #include "qmc_device.h"
+#include "qmc_exp.h"
 
 #include <math.h>
 
@@ -186,31 +187,9 @@ __device__ __forceinline__ double fma_c(double a, double b, double c) {
     return d;
 }
 
-// exp(x) in FP64: Cody-Waite reduction x = n ln2 + r, |r| <= ln2 / 2 (ln2
-// split into a head with trailing zero bits, so n * head is exact, and a
-// tail), the degree-13 Taylor polynomial of e^r (truncation below 5e-18
-// relative), and a scale by 2^n that rounds once, so underflow to
-// subnormals and zero needs no separate branch.  Within 1 ulp of the exact
-// value over the arguments the orbitals use (x <= 0).
-__device__ __forceinline__ double exp_f64(double x) {
-    const double n = __builtin_rint(x * 1.4426950408889634);
-    double r = __builtin_fma(-n, 6.93147180369123816490e-01, x);
-    r = __builtin_fma(-n, 1.90821492927058770002e-10, r);
-    double p = fma_c(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);
-    p = fma_c(p, r, 1.0 / 39916800.0);
-    p = fma_c(p, r, 1.0 / 3628800.0);
-    p = fma_c(p, r, 1.0 / 362880.0);
-    p = fma_c(p, r, 1.0 / 40320.0);
-    p = fma_c(p, r, 1.0 / 5040.0);
-    p = fma_c(p, r, 1.0 / 720.0);
-    p = fma_c(p, r, 1.0 / 120.0);
-    p = fma_c(p, r, 1.0 / 24.0);
-    p = fma_c(p, r, 1.0 / 6.0);
-    p = __builtin_fma(p, r, 0.5);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return __builtin_amdgcn_ldexp(p, (int)n);
-}
+// exp(x) in FP64 (qmc_exp.h), its polynomial's multiply-adds as
+// three-address FMAs.
+__device__ __forceinline__ double exp_f64(double x) { return exp_cody_waite(x, fma_c); }
 
 // 1 / x for x >= 1 (the Pade-type denominators 1 + b r): the hardware
 // reciprocal estimate refined by two Newton steps, within an ulp or so of

@@ -7,7 +7,7 @@ take the same accept decisions and end in the same state.
   H2    1024 walkers x 200 steps, every walker
   LiH   16384 walkers x 500 steps in one block, 24 sampled walkers
   Li2   32768 walkers x 100 steps, 16 sampled walkers
-  CO    65536 walkers, one 10-step launch as bench.py times it, 48 sampled
+  CO    65536 walkers x 500 steps in the benchmark's 10-step launches, 24 sampled
 """
 import numpy as np
 import pytest
@@ -80,7 +80,7 @@ def test_h2_config_every_walker(torch_cuda, oracle_mod):
 
 
 @pytest.mark.parametrize("name,W,n_steps,chunk,n_sample", [
-    ("LiH", 16384, 500, 500, 24), ("Li2", 32768, 100, 100, 16), ("CO", 65536, 10, 10, 48)])
+    ("LiH", 16384, 500, 500, 24), ("Li2", 32768, 100, 100, 16), ("CO", 65536, 500, 10, 24)])
 def test_config_sampled_walkers(torch_cuda, oracle_mod, name, W, n_steps, chunk, n_sample):
     torch = torch_cuda
     sysd = synth.make_system(name)

@@ -262,3 +262,4 @@ def test_backflow_low_rank_row_update():
             assert np.isclose(np.trace(np.linalg.solve(AX, BX)),
                               np.trace(A0i @ B[:, :n]) + np.trace(Z[:, P] @ np.linalg.inv(R) @ A0i[H, :]),
                               rtol=1e-9, atol=1e-9)
+
