@@ -205,17 +205,19 @@ qmc_status qmc_eval_eloc_fd(qmc_system *sys, const double *d_X, int64_t W, doubl
    eq. nabla_loss needs d log|Psi| / d theta, eq. force needs d E_L / d R and
    d ln rho / d R = 2 d log|Psi| / d R).  theta is laid out as
    [primitive exponents in descriptor order | MO coefficients [n_ao][n_mo] in
-   the descriptor's layout | jas_b], qmc_param_count entries; the exponent
-   derivatives include the normalisation's dependence when normalize = 1.
+   the descriptor's layout | jas_b | jas_en [n_atoms][3] when given |
+   jas_een [jas_een_n][7] when given], qmc_param_count entries; the exponent
+   derivatives include the normalisation's dependence when normalize = 1,
+   and the nuclear derivatives include the e-n and e-e-n Jastrow terms'
+   dependence on the nuclei.
      d_dlogpsi      [W][P]  d log|Psi| / d theta
      d_deloc_dtheta [W][P]  d E_L / d theta
      d_dlogpsi_dR   [W][n_atoms][3]  d log|Psi| / d R_alpha
      d_deloc_dR     [W][n_atoms][3]  d E_L / d R_alpha (includes V_nn)
    Any output may be NULL; at least one must not be.  d_X as in
    qmc_eval_psi_eloc.  Returns QMC_EUNSUPPORTED when the walker tables do not
-   fit the 160 KiB of LDS of a compute unit, for systems with many-body
-   Jastrow terms (their parameters have no slot in theta) and for systems
-   with backflow. */
+   fit the 160 KiB of LDS of a compute unit and for systems with
+   backflow. */
 qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
                     double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream);
 

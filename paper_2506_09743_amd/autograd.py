@@ -1,8 +1,9 @@
 """torch.autograd binding of the hand-written adjoint (qmc_grad).
 
 ``Wavefunction`` holds the variational parameters theta = [primitive
-exponents | MO coefficients (n_ao x n_mo, row-major) | Pade b] and the
-nuclear positions R as leaf tensors.  ``psi_eloc(wf, X)`` returns
+exponents | MO coefficients (n_ao x n_mo, row-major) | Pade b | e-n
+parameters per nucleus | e-e-n parameters per term (when the system has
+them)] and the nuclear positions R as leaf tensors.  ``psi_eloc(wf, X)`` returns
 (log|Psi|, sign, E_L) per walker from the HIP evaluation kernel; its backward
 pass calls qmc_grad once and applies the per-walker Jacobians to the incoming
 gradients, so any scalar built from log|Psi| and E_L differentiates to theta
@@ -29,11 +30,25 @@ import torch
 from . import qmc
 
 
+def _jastrow_blocks(sysd: dict):
+    """The many-body Jastrow arrays the system carries, in the qmc_grad order."""
+    out = []
+    if sysd.get("jas_en") is not None:
+        out.append(("jas_en", np.asarray(sysd["jas_en"], dtype=np.float64).shape))
+    een = sysd.get("jas_een")
+    if een is not None and len(een) > 0:
+        out.append(("jas_een", np.asarray(een, dtype=np.float64).shape))
+    return out
+
+
 def pack_theta(sysd: dict) -> np.ndarray:
     """theta in the qmc_grad layout."""
-    return np.concatenate([np.asarray(sysd["prim_exp"], dtype=np.float64).ravel(),
-                           np.asarray(sysd["mo_coef"], dtype=np.float64).ravel(),
-                           [float(sysd.get("jas_b", 1.0))]])
+    parts = [np.asarray(sysd["prim_exp"], dtype=np.float64).ravel(),
+             np.asarray(sysd["mo_coef"], dtype=np.float64).ravel(),
+             [float(sysd.get("jas_b", 1.0))]]
+    for key, _ in _jastrow_blocks(sysd):
+        parts.append(np.asarray(sysd[key], dtype=np.float64).ravel())
+    return np.concatenate(parts)
 
 
 def unpack_theta(sysd: dict, theta, R) -> dict:
@@ -42,12 +57,20 @@ def unpack_theta(sysd: dict, theta, R) -> dict:
     n_prim = int(np.asarray(sysd["prim_exp"]).size)
     shape = np.asarray(sysd["mo_coef"]).shape
     n_mo_coef = shape[0] * shape[1]
-    if theta.shape != (n_prim + n_mo_coef + 1,):
-        raise ValueError(f"theta has shape {theta.shape}, expected ({n_prim + n_mo_coef + 1},)")
+    blocks = _jastrow_blocks(sysd)
+    n = n_prim + n_mo_coef + 1 + sum(int(np.prod(sh)) for _, sh in blocks)
+    if theta.shape != (n,):
+        raise ValueError(f"theta has shape {theta.shape}, expected ({n},)")
     d = dict(sysd)
     d["prim_exp"] = theta[:n_prim].copy()
     d["mo_coef"] = np.ascontiguousarray(theta[n_prim:n_prim + n_mo_coef].reshape(shape))
-    d["jas_b"] = float(theta[-1])
+    q = n_prim + n_mo_coef
+    d["jas_b"] = float(theta[q])
+    q += 1
+    for key, sh in blocks:
+        k = int(np.prod(sh))
+        d[key] = np.ascontiguousarray(theta[q:q + k].reshape(sh))
+        q += k
     d["R"] = np.asarray(R, dtype=np.float64).reshape(-1, 3).copy()
     return d
 

@@ -601,7 +601,9 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     sys->device = device;
     sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
-    sys->n_params = (int64_t)prims.size() + (int64_t)n_ao * d->n_mo + 1;
+    // exponents | MO coefficients | Pade b | e-n (w0, w1, w2) per nucleus | e-e-n 7 per term
+    sys->n_params = (int64_t)prims.size() + (int64_t)n_ao * d->n_mo + 1 + (d->jas_en ? 3 * (int64_t)d->n_atoms : 0) +
+                    7 * (int64_t)d->jas_een_n;
     *out = sys;
     return QMC_OK;
 }
@@ -694,7 +696,7 @@ qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlo
     if (W == 0) return QMC_OK;
     if (!d_X || (!d_dlogpsi && !d_deloc_dtheta && !d_dlogpsi_dR && !d_deloc_dR)) return QMC_EINVAL;
     if (qmc::grad_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
-    if (sys->S.jas_en || sys->S.een_n > 0 || sys->S.bf_omega != 0.0) return QMC_EUNSUPPORTED;
+    if (sys->S.bf_omega != 0.0) return QMC_EUNSUPPORTED;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
     hipError_t e = qmc::launch_grad(sys->S, d_X, W, d_dlogpsi, d_deloc_dtheta, d_dlogpsi_dR, d_deloc_dR,

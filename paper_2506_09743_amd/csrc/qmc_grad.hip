@@ -1,8 +1,10 @@
 // Hand-written adjoint of log|Psi| and E_L (gfx950, FP64): derivatives with
-// respect to the primitive exponents, the MO coefficients and the Pade
-// parameter b (Methods, eq. nabla_loss needs d log|Psi| / d theta), and with
-// respect to the nuclear positions (Methods, eq. force needs d E_L / d R and
-// d ln rho / d R = 2 d log|Psi| / d R).
+// respect to the primitive exponents, the MO coefficients and the Jastrow
+// parameters (Pade b; the e-n and e-e-n parameters of the many-body
+// appendix when present) (Methods, eq. nabla_loss needs d log|Psi| / d theta),
+// and with respect to the nuclear positions (Methods, eq. force needs
+// d E_L / d R and d ln rho / d R = 2 d log|Psi| / d R).  The Jastrow part is
+// differentiated in forward mode (Dual numbers through the Jastrow stage).
 //
 // With a_e[m] = d log Sigma / d phi_m(r_e) from the shared stages:
 //   d log|Psi| / d theta = sum_e sum_mu t_mu d chi_mu(r_e) / d theta,
@@ -48,15 +50,23 @@ struct GradOut {
 // and the per-electron rows [LW][2 n_ao + 2 NMO] (chi, beta, a, adot) take
 // the block from 0.  The per-nucleus results [n_atoms][6] live past the end
 // of both.
+// After the MO-coefficient gradient the same block holds the walker's
+// positions [LW][3] and the Dual e-e-n tables of the Jastrow directions
+// (2 doubles per entry): [LW][n_atoms][2 een_n] factors, [LW][n_atoms][4]
+// geometry.
+__host__ __device__ inline int grad_dual_size(const DevSystem &S) {
+    return 3 * S.LW + 2 * S.LW * S.n_atoms * (2 * S.een_n + 4);
+}
+
 template <int NMO>
 __host__ __device__ inline int grad_rows_end(const DevSystem &S) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
     const int base = walker_lds<NMO>(S);
     const int fwd = base + 6 * nmax * NMO;
     const int rows = S.LW * (2 * S.n_ao + 2 * NMO);
-    const int pos = base + 3 * S.LW;
     int e = fwd > rows ? fwd : rows;
-    return e > pos ? e : pos;
+    const int dual = grad_dual_size(S);
+    return e > dual ? e : dual;
 }
 
 template <int NMO>
@@ -162,7 +172,6 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
     double *gx = wsm + base_lds;               // gradient-only region
     double *sTD = gx, *sCD = gx + 2 * ts, *sZB = gx + 4 * ts;
     const int rows_len = 2 * S.n_ao + 2 * NMO;
-    double *sPos = gx;                         // [LW][3], before the shared stages
     double *sRows = wsm;                       // after the forward-mode stage
     double *sAtom = wsm + grad_rows_end<NMO>(S);  // [n_atoms][6]: dlogpsi/dR, dE/dR
 
@@ -179,33 +188,7 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
         x2 = 100.0;
     }
 
-    // ---- b-derivatives of the Jastrow terms (positions kept for them) ------
-    sPos[3 * L.lw + 0] = x0;
-    sPos[3 * L.lw + 1] = x1;
-    sPos[3 * L.lw + 2] = x2;
     for (int q = L.lw; q < 6 * S.n_atoms; q += S.LW) sAtom[q] = 0.0;
-    __syncthreads();
-    double dJ_db = 0.0, dgJ0 = 0.0, dgJ1 = 0.0, dgJ2 = 0.0, dlapJ = 0.0;
-    if (L.active) {
-        for (int j = 0; j < S.ne; ++j) {
-            if (j == L.e) continue;
-            const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
-            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const bool same = (j < S.n_up) == (L.e < S.n_up);
-            const double a = same ? S.a_par : S.a_anti;
-            const double den = 1.0 + S.b * r;
-            const double i2 = 1.0 / (den * den), i3 = i2 / den, i4 = i3 / den;
-            dJ_db += 0.5 * (-a * r * r * i2);
-            const double dk1 = -2.0 * a * r * i3;                         // d K' / d b
-            const double dk2 = -2.0 * a * i3 + 6.0 * a * S.b * r * i4;    // d K'' / d b
-            dgJ0 += dk1 * d0 / r;
-            dgJ1 += dk1 * d1 / r;
-            dgJ2 += dk1 * d2 / r;
-            dlapJ += dk2 + 2.0 * dk1 / r;
-        }
-    }
-    __syncthreads();
 
     // ---- shared stages: MO values, Gauss-Jordan, determinants, a_e ----------
     Core<NMO> c;
@@ -501,17 +484,60 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
         }
     }
 
-    // Pade parameter b
-    double pb = 0.0;
-    if (L.active)
-        pb = -0.5 * (dlapJ + 2.0 * (c.gJ0 * dgJ0 + c.gJ1 * dgJ1 + c.gJ2 * dgJ2) +
-                     2.0 * (dgJ0 * gS[0] + dgJ1 * gS[1] + dgJ2 * gS[2]));
-    const double dEb = walker_sum(pb, S.LW);
-    const double dlb = walker_sum(dJ_db, S.LW);
+    // ---- Jastrow parameters and the Jastrow part of the nuclear gradients ---
+    // Forward mode over the Jastrow stage: each direction seeds one Jastrow
+    // parameter (Pade b, e-n (w0, w1, w2) per nucleus, e-e-n (c, a1, b1, a2,
+    // b2, a3, b3) per term) or, when the Jastrow depends on the nuclei, one
+    // nuclear coordinate.  d log|Psi| = d J and
+    // d E_L = -1/2 sum_e (d lap_e J + 2 grad_e J . d grad_e J + 2 d grad_e J . grad_e Sigma / Sigma).
+    __syncthreads();  // the per-electron rows are no longer read
+    {
+        double *sP = wsm;                                   // [LW][3]
+        Dual *dF = (Dual *)(wsm + 3 * S.LW);                // [LW][n_atoms][2 een_n]
+        Dual *dG = dF + S.LW * S.n_atoms * 2 * S.een_n;     // [LW][n_atoms][4]
+        sP[3 * L.lw + 0] = x0;
+        sP[3 * L.lw + 1] = x1;
+        sP[3 * L.lw + 2] = x2;
+        const int n_en = S.jas_en ? 3 * S.n_atoms : 0, n_een = 7 * S.een_n;
+        const bool jas_R = (S.jas_en || S.een_n > 0) && (G.dlogpsi_dR || G.deloc_dR);
+        const int n_dir = 1 + n_en + n_een + (jas_R ? 3 * S.n_atoms : 0);
+        const int p_b = S.n_prim + S.n_ao * S.n_mo;        // output index of b
+        for (int dir = 0; dir < n_dir; ++dir) {
+            int kind, i, k, out;
+            if (dir == 0) {
+                kind = 0, i = 0, k = 0, out = p_b;
+            } else if (dir <= n_en) {
+                kind = 1, i = (dir - 1) / 3, k = (dir - 1) % 3, out = p_b + dir;
+            } else if (dir <= n_en + n_een) {
+                kind = 2, i = (dir - 1 - n_en) / 7, k = (dir - 1 - n_en) % 7, out = p_b + dir;
+            } else {
+                kind = 3, i = (dir - 1 - n_en - n_een) / 3, k = (dir - 1 - n_en - n_een) % 3, out = -1;
+            }
+            const SeedPrm sp{S, kind, i, k};
+            een_table_fill<Dual>(S, L, x0, x1, x2, dF, dG, sp);
+            __syncthreads();
+            const JasTerms<Dual> jd = jastrow_terms<Dual>(S, L, x0, x1, x2, sP, dF, dG, sp);
+            double dl = 0.0, de = 0.0;
+            if (L.active) {
+                dl = jd.J.d;
+                de = -0.5 * (jd.lap.d + 2.0 * (gJ[0] * jd.g0.d + gJ[1] * jd.g1.d + gJ[2] * jd.g2.d) +
+                             2.0 * (jd.g0.d * gS[0] + jd.g1.d * gS[1] + jd.g2.d * gS[2]));
+            }
+            dl = walker_sum(dl, S.LW);
+            de = walker_sum(de, S.LW);
+            if (L.wvalid && L.lw == 0) {
+                if (out >= 0) {
+                    if (G.dlogpsi) G.dlogpsi[w * G.n_param + out] = dl;
+                    if (G.deloc_dth) G.deloc_dth[w * G.n_param + out] = de;
+                } else {
+                    sAtom[6 * i + k] += dl;
+                    sAtom[6 * i + 3 + k] += de;
+                }
+            }
+            __syncthreads();  // the tables are rewritten by the next direction
+        }
+    }
     if (L.wvalid && L.lw == 0) {
-        const int out = G.n_param - 1;
-        if (G.dlogpsi) G.dlogpsi[w * G.n_param + out] = dlb;
-        if (G.deloc_dth) G.deloc_dth[w * G.n_param + out] = dEb;
         // nuclear gradients, with the n-n repulsion
         for (int a = 0; a < S.n_atoms; ++a) {
             const double *A = S.atoms + 4 * a;

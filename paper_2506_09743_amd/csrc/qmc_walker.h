@@ -509,6 +509,195 @@ __host__ __device__ inline int walker_lds(const DevSystem &S) {
     return tc > pp ? tc : pp;
 }
 
+// ---- Jastrow stage, generic in its scalar type ------------------------------
+// The evaluation runs it on doubles; the adjoint runs it on Dual numbers
+// (value and one directional derivative) to differentiate J, grad_e J and
+// lap_e J with respect to a Jastrow parameter or a nuclear coordinate
+// (forward mode).  Parameters come through an accessor: PlainPrm returns
+// the system's values, SeedPrm the same values as Duals with derivative 1 on
+// one chosen entry.
+struct Dual {
+    double v, d;
+    __device__ Dual() : v(0.0), d(0.0) {}
+    __device__ explicit Dual(double x) : v(x), d(0.0) {}
+    __device__ Dual(double x, double dx) : v(x), d(dx) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+    const double q = a.v / b.v;
+    return Dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+__device__ __forceinline__ Dual operator/(double a, Dual b) {
+    const double q = a / b.v;
+    return Dual(q, -q * b.d / b.v);
+}
+__device__ __forceinline__ Dual &operator+=(Dual &a, Dual b) { return a = a + b; }
+__device__ __forceinline__ Dual &operator-=(Dual &a, Dual b) { return a = a - b; }
+using ::sqrt;  // the overload below must not hide the double one
+__device__ __forceinline__ Dual sqrt(Dual a) {
+    const double r = ::sqrt(a.v);
+    return Dual(r, 0.5 * a.d / r);
+}
+__device__ __forceinline__ Dual rcp_ge1(Dual x) {
+    const double y = rcp_ge1(x.v);
+    return Dual(y, -x.d * y * y);
+}
+__device__ __forceinline__ double value_of(double x) { return x; }
+__device__ __forceinline__ double value_of(Dual x) { return x.v; }
+
+struct PlainPrm {
+    const DevSystem &S;
+    __device__ double b() const { return S.b; }
+    __device__ double R(int a, int k) const { return S.atoms[4 * a + k]; }
+    __device__ double en(int a, int k) const { return S.jas_en[3 * a + k]; }
+    __device__ double een(int m, int k) const { return S.jas_een[7 * m + k]; }
+};
+
+// Seeded entry: kind 0 the Pade b, 1 the e-n parameter (i, k), 2 the e-e-n
+// parameter (i, k), 3 the coordinate k of nucleus i; -1 none.
+struct SeedPrm {
+    const DevSystem &S;
+    int kind, i, k;
+    __device__ Dual b() const { return Dual(S.b, kind == 0 ? 1.0 : 0.0); }
+    __device__ Dual R(int a, int kk) const { return Dual(S.atoms[4 * a + kk], (kind == 3 && a == i && kk == k) ? 1.0 : 0.0); }
+    __device__ Dual en(int a, int kk) const { return Dual(S.jas_en[3 * a + kk], (kind == 1 && a == i && kk == k) ? 1.0 : 0.0); }
+    __device__ Dual een(int m, int kk) const { return Dual(S.jas_een[7 * m + kk], (kind == 2 && m == i && kk == k) ? 1.0 : 0.0); }
+};
+
+// The lane's e-e-n factor table: per nucleus a, [een_n][2] factor values
+// f(a1, b1; u) and f(a2, b2; u) of its electron at u = r_a e, then [4] the
+// geometry (u and the unit vector from the nucleus).  T values, LDS.
+template <typename T, typename Prm>
+__device__ __forceinline__ void een_table_fill(const DevSystem &S, const Lane &L, double x0, double x1, double x2,
+                                               T *sF, T *sG, const Prm &prm) {
+    if (S.een_n == 0 || !L.active) return;
+    for (int a = 0; a < S.n_atoms; ++a) {
+        const T e0 = x0 - prm.R(a, 0), e1 = x1 - prm.R(a, 1), e2 = x2 - prm.R(a, 2);
+        const T u = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        const T ui = 1.0 / u;
+        T *g = sG + (L.lw * S.n_atoms + a) * 4;
+        g[0] = u;
+        g[1] = e0 * ui;
+        g[2] = e1 * ui;
+        g[3] = e2 * ui;
+        T *f = sF + (L.lw * S.n_atoms + a) * 2 * S.een_n;
+        for (int m = 0; m < S.een_n; ++m) {
+            f[2 * m] = prm.een(m, 1) * u * rcp_ge1(1.0 + prm.een(m, 2) * u);
+            f[2 * m + 1] = prm.een(m, 3) * u * rcp_ge1(1.0 + prm.een(m, 4) * u);
+        }
+    }
+}
+
+template <typename T>
+struct JasTerms {
+    T J, g0, g1, g2, lap;
+    double vpot;  // Coulomb terms of the electron (evaluated when T is double)
+};
+
+// Jastrow factor (eq. jastrow: Pade e-e kernel of eq. pade_kernel, e-n and
+// e-e-n kernels of the many-body appendix) of the lane's electron: its share
+// of J, grad_e J and lap_e J; with T = double also its Coulomb terms
+// (eq. Hmol: half of each e-e pair, the e-n attraction).  sPos holds the
+// walker's positions, sF / sG the e-e-n tables of een_table_fill.
+template <typename T, typename Prm>
+__device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const Lane &L, double x0, double x1,
+                                                     double x2, const double *sPos, const T *sF, const T *sG,
+                                                     const Prm &prm) {
+    constexpr bool kPlain = sizeof(T) == sizeof(double);
+    JasTerms<T> o;
+    o.J = T(0.0);
+    o.g0 = T(0.0);
+    o.g1 = T(0.0);
+    o.g2 = T(0.0);
+    o.lap = T(0.0);
+    o.vpot = 0.0;
+    if (!L.active) return o;
+    const T b = prm.b();
+    for (int j = 0; j < S.ne; ++j) {
+        if (j == L.e) continue;
+        const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
+        const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const bool same = (j < S.n_up) == (L.e < S.n_up);
+        const double a = same ? S.a_par : S.a_anti;
+        // one division gives both 1/r and 1/(1 + b r)
+        const T den = 1.0 + b * r;
+        const T q = 1.0 / (r * den);
+        const T rinv = q * den, dinv = q * r;
+        const T k1 = a * dinv * dinv;                 // K'(r)
+        const T k2 = -2.0 * a * b * dinv * dinv * dinv;  // K''(r)
+        o.J += 0.5 * a * r * dinv;
+        o.g0 += k1 * d0 * rinv;
+        o.g1 += k1 * d1 * rinv;
+        o.g2 += k1 * d2 * rinv;
+        o.lap += k2 + 2.0 * k1 * rinv;
+        if constexpr (kPlain) o.vpot += 0.5 * rinv;
+    }
+    for (int a = 0; a < S.n_atoms; ++a) {
+        const T d0 = x0 - prm.R(a, 0), d1 = x1 - prm.R(a, 1), d2 = x2 - prm.R(a, 2);
+        if constexpr (kPlain) o.vpot -= S.atoms[4 * a + 3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (S.jas_en) {
+            // e-n kernel K = N / D, N = w0 r + w1 r^2, D = 1 + w2 r:
+            // K' = (N' - K D') / D and K'' = (N'' - 2 K' D') / D
+            const T r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const T w0 = prm.en(a, 0), w1 = prm.en(a, 1), w2 = prm.en(a, 2);
+            const T q = 1.0 / (1.0 + w2 * r), rinv = 1.0 / r;
+            const T K = (w0 + w1 * r) * r * q;
+            const T K1 = (w0 + 2.0 * w1 * r - K * w2) * q;
+            const T K2 = (2.0 * w1 - 2.0 * K1 * w2) * q;
+            o.J += K;
+            o.g0 += K1 * d0 * rinv;
+            o.g1 += K1 * d1 * rinv;
+            o.g2 += K1 * d2 * rinv;
+            o.lap += K2 + 2.0 * K1 * rinv;
+        }
+    }
+    // e-e-n kernel: for the ordered pair (i, j), i > j, the term is
+    // c f1(r_ai) f2(r_aj) f3(r_ij).  This electron takes the role of i
+    // against lower-numbered partners and of j against higher ones; its
+    // own factor carries the derivatives, the partner's factor is a value
+    // from the table.  The pair's value is counted at i.
+    for (int j = 0; j < S.ne && S.een_n > 0; ++j) {
+        if (j == L.e) continue;
+        const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
+        const bool first = L.e > j;
+        const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double rinv = 1.0 / r;
+        const double w0 = d0 * rinv, w1 = d1 * rinv, w2 = d2 * rinv;
+        for (int m = 0; m < S.een_n; ++m) {
+            const T a3 = prm.een(m, 5), b3 = prm.een(m, 6);
+            const T q3 = rcp_ge1(1.0 + b3 * r);
+            const T f3 = a3 * r * q3, f31 = a3 * q3 * q3, f32 = -2.0 * b3 * f31 * q3;
+            const T ao = first ? prm.een(m, 1) : prm.een(m, 3), bo = first ? prm.een(m, 2) : prm.een(m, 4);
+            const T cm = prm.een(m, 0);
+            for (int a = 0; a < S.n_atoms; ++a) {
+                const T *g = sG + (L.lw * S.n_atoms + a) * 4;
+                const T u = g[0];
+                const T qo = rcp_ge1(1.0 + bo * u);
+                const T fo = ao * u * qo, fo1 = ao * qo * qo, fo2 = -2.0 * bo * fo1 * qo;
+                const T cp = cm * sF[((lj * S.n_atoms + a) * S.een_n + m) * 2 + (first ? 1 : 0)];
+                const T uw = g[1] * w0 + g[2] * w1 + g[3] * w2;
+                if (first) o.J += cp * fo * f3;
+                o.g0 += cp * (fo1 * f3 * g[1] + fo * f31 * w0);
+                o.g1 += cp * (fo1 * f3 * g[2] + fo * f31 * w1);
+                o.g2 += cp * (fo1 * f3 * g[3] + fo * f31 * w2);
+                o.lap += cp * ((fo2 + 2.0 * fo1 / u) * f3 + 2.0 * fo1 * f31 * uw + fo * (f32 + 2.0 * f31 * rinv));
+            }
+        }
+    }
+    return o;
+}
+
 // Per-lane results of the stages every evaluation shares.
 template <int NMO>
 struct Core {
@@ -571,104 +760,13 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     sPos[3 * L.lw + 0] = x0;
     sPos[3 * L.lw + 1] = x1;
     sPos[3 * L.lw + 2] = x2;
-    if (S.een_n > 0 && L.active) {
-        for (int a = 0; a < S.n_atoms; ++a) {
-            const double *A = S.atoms + 4 * a;
-            const double e0 = x0 - A[0], e1 = x1 - A[1], e2 = x2 - A[2];
-            const double u = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-            const double ui = 1.0 / u;
-            double *g = sG + (L.lw * S.n_atoms + a) * 4;
-            g[0] = u;
-            g[1] = e0 * ui;
-            g[2] = e1 * ui;
-            g[3] = e2 * ui;
-            double *f = sF + (L.lw * S.n_atoms + a) * 2 * S.een_n;
-            for (int m = 0; m < S.een_n; ++m) {
-                const double *q = S.jas_een + 7 * m;
-                f[2 * m] = q[1] * u * rcp_ge1(1.0 + q[2] * u);
-                f[2 * m + 1] = q[3] * u * rcp_ge1(1.0 + q[4] * u);
-            }
-        }
-    }
+    const PlainPrm prm{S};
+    een_table_fill<double>(S, L, x0, x1, x2, sF, sG, prm);
     __syncthreads();
 
-    // ---- Pade e-e Jastrow and Coulomb terms of this electron (FP64) --------
-    double J = 0.0, gJ0 = 0.0, gJ1 = 0.0, gJ2 = 0.0, lapJ = 0.0, vpot = 0.0;
-    if (L.active) {
-        for (int j = 0; j < S.ne; ++j) {
-            if (j == L.e) continue;
-            const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
-            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const bool same = (j < S.n_up) == (L.e < S.n_up);
-            const double a = same ? S.a_par : S.a_anti, b = S.b;
-            // one division gives both 1/r and 1/(1 + b r)
-            const double den = 1.0 + b * r;
-            const double q = 1.0 / (r * den);
-            const double rinv = q * den, dinv = q * r;
-            const double k1 = a * dinv * dinv;                // K'(r)
-            const double k2 = -2.0 * a * b * dinv * dinv * dinv;  // K''(r)
-            J += 0.5 * a * r * dinv;
-            gJ0 += k1 * d0 * rinv;
-            gJ1 += k1 * d1 * rinv;
-            gJ2 += k1 * d2 * rinv;
-            lapJ += k2 + 2.0 * k1 * rinv;
-            vpot += 0.5 * rinv;
-        }
-        for (int a = 0; a < S.n_atoms; ++a) {
-            const double *A = S.atoms + 4 * a;
-            const double d0 = x0 - A[0], d1 = x1 - A[1], d2 = x2 - A[2];
-            vpot -= A[3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            if (S.jas_en) {
-                // e-n kernel K = N / D, N = w0 r + w1 r^2, D = 1 + w2 r:
-                // K' = (N' - K D') / D and K'' = (N'' - 2 K' D') / D
-                const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-                const double *w = S.jas_en + 3 * a;
-                const double q = 1.0 / (1.0 + w[2] * r), rinv = 1.0 / r;
-                const double K = (w[0] + w[1] * r) * r * q;
-                const double K1 = (w[0] + 2.0 * w[1] * r - K * w[2]) * q;
-                const double K2 = (2.0 * w[1] - 2.0 * K1 * w[2]) * q;
-                J += K;
-                gJ0 += K1 * d0 * rinv;
-                gJ1 += K1 * d1 * rinv;
-                gJ2 += K1 * d2 * rinv;
-                lapJ += K2 + 2.0 * K1 * rinv;
-            }
-        }
-        // e-e-n kernel: for the ordered pair (i, j), i > j, the term is
-        // c f1(r_ai) f2(r_aj) f3(r_ij).  This electron takes the role of i
-        // against lower-numbered partners and of j against higher ones; its
-        // own factor carries the derivatives, the partner's factor is a
-        // value from the table.  The pair's value is counted at i.
-        for (int j = 0; j < S.ne && S.een_n > 0; ++j) {
-            if (j == L.e) continue;
-            const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
-            const bool first = L.e > j;
-            const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double rinv = 1.0 / r;
-            const double w0 = d0 * rinv, w1 = d1 * rinv, w2 = d2 * rinv;
-            for (int m = 0; m < S.een_n; ++m) {
-                const double *q = S.jas_een + 7 * m;
-                const double q3 = rcp_ge1(1.0 + q[6] * r);
-                const double f3 = q[5] * r * q3, f31 = q[5] * q3 * q3, f32 = -2.0 * q[6] * f31 * q3;
-                const double ao = first ? q[1] : q[3], bo = first ? q[2] : q[4];
-                for (int a = 0; a < S.n_atoms; ++a) {
-                    const double *g = sG + (L.lw * S.n_atoms + a) * 4;
-                    const double u = g[0];
-                    const double qo = rcp_ge1(1.0 + bo * u);
-                    const double fo = ao * u * qo, fo1 = ao * qo * qo, fo2 = -2.0 * bo * fo1 * qo;
-                    const double cp = q[0] * sF[((lj * S.n_atoms + a) * S.een_n + m) * 2 + (first ? 1 : 0)];
-                    const double uw = g[1] * w0 + g[2] * w1 + g[3] * w2;
-                    if (first) J += cp * fo * f3;
-                    gJ0 += cp * (fo1 * f3 * g[1] + fo * f31 * w0);
-                    gJ1 += cp * (fo1 * f3 * g[2] + fo * f31 * w1);
-                    gJ2 += cp * (fo1 * f3 * g[3] + fo * f31 * w2);
-                    lapJ += cp * ((fo2 + 2.0 * fo1 / u) * f3 + 2.0 * fo1 * f31 * uw + fo * (f32 + 2.0 * f31 * rinv));
-                }
-            }
-        }
-    }
+    // ---- Jastrow and Coulomb terms of this electron (FP64) ----------------
+    const JasTerms<double> jt = jastrow_terms<double>(S, L, x0, x1, x2, sPos, sF, sG, prm);
+    const double J = jt.J, gJ0 = jt.g0, gJ1 = jt.g1, gJ2 = jt.g2, lapJ = jt.lap, vpot = jt.vpot;
 
     c.J = J;
     c.gJ0 = gJ0;

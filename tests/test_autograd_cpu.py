@@ -37,3 +37,25 @@ def test_theta_shape_rejected():
     sysd = synth.make_system("LiH")
     with pytest.raises(ValueError):
         ag.unpack_theta(sysd, ag.pack_theta(sysd)[:-1], sysd["R"])
+
+
+def test_theta_round_trip_many_body():
+    """With the many-body Jastrow the layout continues with the e-n
+    parameters per nucleus and the e-e-n parameters per term."""
+    from paper_2506_09743_amd import autograd as ag
+    sysd = synth.with_many_body_jastrow(synth.make_system("Li2"), 3)
+    th = ag.pack_theta(sysd)
+    n_prim = sysd["prim_exp"].size
+    nao, nmo = sysd["mo_coef"].shape
+    p_b = n_prim + nao * nmo
+    assert th.shape == (p_b + 1 + sysd["jas_en"].size + sysd["jas_een"].size,)
+    assert th[p_b] == sysd["jas_b"]
+    assert th[p_b + 1 + 3 * 1 + 2] == sysd["jas_en"][1, 2]
+    assert th[p_b + 1 + sysd["jas_en"].size + 7 * 2 + 4] == sysd["jas_een"][2, 4]
+    th2 = th.copy()
+    th2[p_b + 2] += 0.25
+    th2[-1] += 0.5
+    d = ag.unpack_theta(sysd, th2, sysd["R"])
+    assert d["jas_en"][0, 1] == sysd["jas_en"][0, 1] + 0.25
+    assert d["jas_een"][-1, -1] == sysd["jas_een"][-1, -1] + 0.5
+    assert np.array_equal(ag.pack_theta(d), th2)

@@ -1,6 +1,7 @@
 """qmc_grad (hand-written adjoint) against central finite differences of the
 FP64 oracle, h = 1e-5, for every variational parameter (primitive exponents,
-MO coefficients, Pade b) and every nuclear coordinate:
+MO coefficients, Pade b, and with the many-body Jastrow every e-n and e-e-n
+parameter) and every nuclear coordinate:
 
   d log|Psi| / d theta,  d E_L / d theta,  d log|Psi| / d R,  d E_L / d R.
 
@@ -31,6 +32,8 @@ def _perturbed(sysd, kind, idx, h):
         d["jas_b"] = sysd["jas_b"] + h
     elif kind == "R":
         d["R"][idx] += h
+    elif kind in ("jas_en", "jas_een"):
+        d[kind][idx] += h
     return d
 
 
@@ -48,46 +51,60 @@ def _check(name, ana, fd, what):
     assert worst < 2e-6, f"{name} {what}: {worst}"
 
 
-@pytest.mark.parametrize("name,nw", [("Li2", 4), ("LiH", 4), ("CO", 2), ("H2", 4)])
-def test_grad_vs_oracle_fd(oracle_mod, name, nw):
+@pytest.mark.parametrize("name,nw,mbj", [("Li2", 4, False), ("LiH", 4, False), ("CO", 2, False), ("H2", 4, False),
+                                         ("Li2", 3, True), ("LiH", 3, True), ("CO", 2, True)])
+def test_grad_vs_oracle_fd(oracle_mod, name, nw, mbj):
     import torch
     from paper_2506_09743_amd import qmc
     sysd = synth.make_system(name)
+    if mbj:
+        # many-body terms with amplified e-e-n weights so their derivatives matter
+        sysd = synth.with_many_body_jastrow(sysd, synth.MBJ_SEED[name], symmetric=False)
+        sysd["jas_een"][:, 0] *= 10.0
     o = oracle_mod.OracleSystem(sysd)
     X = _good_walkers(o, sysd, nw, 11)
     s = qmc.System(sysd)
     dl, de, dlR, deR = [t.cpu().numpy() for t in s.grad(torch.from_numpy(X).cuda())]
     n_prim = sysd["prim_exp"].size
     nao, nmo = sysd["mo_coef"].shape
-    assert dl.shape[1] == n_prim + nao * nmo + 1
+    p_b = n_prim + nao * nmo
+    n_en = sysd["jas_en"].size if mbj else 0
+    n_een = sysd["jas_een"].size if mbj else 0
+    assert dl.shape[1] == p_b + 1 + n_en + n_een == s.param_count
     rng = np.random.default_rng(0)
-    # every exponent, b, and a sample of MO coefficients (all of them for small systems)
-    cols = list(range(n_prim)) + [dl.shape[1] - 1]
+    # every exponent, b, every many-body parameter and a sample of MO
+    # coefficients (all of them for small systems)
+    cols = list(range(n_prim)) + list(range(p_b, p_b + 1 + n_en + n_een))
     mo_idx = np.arange(nao * nmo)
     if nao * nmo > 120:
-        mo_idx = rng.choice(mo_idx, 120, replace=False)
+        mo_idx = rng.choice(mo_idx, 120 if not mbj else 40, replace=False)
     cols += [n_prim + int(q) for q in mo_idx]
     fd_l = np.zeros((nw, len(cols)))
     fd_e = np.zeros((nw, len(cols)))
     for j, c in enumerate(cols):
         if c < n_prim:
             kind, idx = "exp", c
-        elif c == dl.shape[1] - 1:
+        elif c == p_b:
             kind, idx = "b", None
+        elif c > p_b and c <= p_b + n_en:
+            kind, idx = "jas_en", np.unravel_index(c - p_b - 1, sysd["jas_en"].shape)
+        elif c > p_b + n_en:
+            kind, idx = "jas_een", np.unravel_index(c - p_b - 1 - n_en, sysd["jas_een"].shape)
         else:
             q = c - n_prim
             kind, idx = "mo", (q // nmo, q % nmo)
         fd_l[:, j], fd_e[:, j] = _fd(oracle_mod, sysd, X, kind, idx)
-    _check(name, dl[:, cols], fd_l, "dlog|Psi|/dtheta")
-    _check(name, de[:, cols], fd_e, "dE_L/dtheta")
+    tag = name + (" + many-body" if mbj else "")
+    _check(tag, dl[:, cols], fd_l, "dlog|Psi|/dtheta")
+    _check(tag, de[:, cols], fd_e, "dE_L/dtheta")
     na = len(sysd["Z"])
     fl = np.zeros((nw, na * 3))
     fe = np.zeros((nw, na * 3))
     for a in range(na):
         for k in range(3):
             fl[:, 3 * a + k], fe[:, 3 * a + k] = _fd(oracle_mod, sysd, X, "R", (a, k))
-    _check(name, dlR.reshape(nw, -1), fl, "dlog|Psi|/dR")
-    _check(name, deR.reshape(nw, -1), fe, "dE_L/dR")
+    _check(tag, dlR.reshape(nw, -1), fl, "dlog|Psi|/dR")
+    _check(tag, deR.reshape(nw, -1), fe, "dE_L/dR")
     s.close()
 
 

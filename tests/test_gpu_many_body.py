@@ -129,13 +129,27 @@ def test_mbj_zero_parameters_equal_pade(torch_cuda):
     b.close()
 
 
-def test_mbj_grad_declined(torch_cuda):
+def test_mbj_grad_zero_terms_equal_pade(torch_cuda):
+    """With zero e-n parameters and zero e-e-n weights the adjoint's outputs
+    on the shared parameters (exponents, MO coefficients, b) and on the
+    nuclei equal the Pade-only system's; the added entries are finite."""
     from paper_2506_09743_amd import qmc
     torch = torch_cuda
-    sysd = _mbj("LiH")
-    s = qmc.System(sysd)
-    X = torch.from_numpy(synth.init_walkers(sysd, 8, 1)).cuda()
-    with pytest.raises(qmc.QmcError) as e:
-        s.grad(X)
-    assert e.value.status == qmc.QMC_EUNSUPPORTED
-    s.close()
+    base = synth.make_system("LiH")
+    d = synth.with_many_body_jastrow(base, 1)
+    d["jas_en"] = np.zeros_like(d["jas_en"])
+    d["jas_een"] = d["jas_een"].copy()
+    d["jas_een"][:, 0] = 0.0
+    X = torch.from_numpy(synth.init_walkers(base, 64, 1)).cuda()
+    a, b = qmc.System(base), qmc.System(d)
+    ga, gb = [[t.cpu().numpy() for t in s.grad(X)] for s in (a, b)]
+    P = a.param_count
+    assert b.param_count == P + d["jas_en"].size + d["jas_een"].size
+    ok = np.all(np.isfinite(ga[0]), axis=1)
+    for k in (0, 1):
+        assert np.allclose(ga[k][ok], gb[k][ok][:, :P], rtol=1e-12, atol=1e-12)
+        assert np.all(np.isfinite(gb[k][ok][:, P:]))
+    for k in (2, 3):
+        assert np.allclose(ga[k][ok], gb[k][ok], rtol=1e-12, atol=1e-10)
+    a.close()
+    b.close()
