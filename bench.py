@@ -157,21 +157,47 @@ def backflow_flops_per_walker_step(sysd, low_rank: bool = True) -> dict:
 
 
 def grad_flops_per_walker(sysd) -> dict:
-    """Algorithmic FP operations of one walker's qmc_grad (estimate from the
-    shapes): the forward Psi / E_L evaluation, the forward-mode determinant
-    algebra for the Hessian-vector product, the MO-coefficient outer
-    products of both outputs, the exponent derivatives per primitive and
-    electron, and the AO Hessian / grad-Laplacian contractions per nucleus."""
+    """Algorithmic FP operations of one walker's qmc_grad, term by term from
+    the adjoint's formulas (same counting rules as flops_per_walker_step;
+    a Dual operation counts as the value's and the derivative's flops):
+      forward      the evaluation (Psi, E_L) without proposal and accept
+      direction_B  B[e][m] = sum_mu C[mu][m] (lap chi + 2 grad J . grad chi):
+                   radial sums with second derivatives per primitive, AO
+                   gradient and beta per AO, the contraction 2 n_ao n_mo
+      fwd_dets     Z = B - B0 T, Tdot = A0^-1 Z, Ainvdot, rho_dot and Sdot per
+                   determinant, Cdot per cofactor contribution, adot
+      main_pass    per electron and AO: t = C a and tdot = C adot (4 n_mo),
+                   grad chi, (Hess chi) . grad J, grad lap chi and the force
+                   sums; per primitive the exponent derivatives
+      mo_coef      chi (x) a and adot (x) chi + a (x) beta over the electrons
+      jastrow_dirs one Dual pass of the Jastrow stage per direction (b, the
+                   many-body parameters, the nuclear coordinates when the
+                   Jastrow depends on them)"""
     from paper_2506_09743_amd import synth
     fw = flops_per_walker_step(sysd)
     ne, nao = synth.n_elec(sysd), synth.n_ao(sysd)
+    nu, nd = int(sysd["n_up"]), int(sysd["n_dn"])
     nmo = int(np.asarray(sysd["mo_coef"]).shape[1])
     n_prim = int(np.asarray(sysd["prim_exp"]).size)
-    f = {"forward": fw["total"] - fw["proposal"] - fw["accept"],
-         "forward_mode_dets": fw["lu"] + fw["dets"] + fw["cofactors"] + fw["traces"],
-         "mo_coef": 3 * 2 * ne * nao * nmo,
-         "exponents": ne * n_prim * 30,
-         "nuclei": ne * nao * 40}
+    na = len(sysd["Z"])
+    ndet = len(sysd["ci"])
+    n_en = 3 * na if sysd.get("jas_en") is not None else 0
+    n_een = 0 if sysd.get("jas_een") is None else int(np.asarray(sysd["jas_een"]).shape[0])
+    f = {"forward": fw["total"] - fw["proposal"] - fw["accept"]}
+    f["direction_B"] = ne * (n_prim * 30 + nao * 30 + 2 * nao * nmo)
+    fd = 0
+    for n in (nu, nd):
+        fd += 2 * n * n * (nmo - n) + 2 * n ** 3 + 2 * n * n * nmo + 8 * n * (nmo - n) * n
+    f["fwd_dets"] = fd + ndet * 16 + fw["cofactors"] * 2
+    f["main_pass"] = ne * (n_prim * 30 + nao * (4 * nmo + 80) + n_prim * 40)
+    f["mo_coef"] = 6 * ne * nao * nmo
+    # each direction evaluates only the terms that depend on its entry
+    dirs = ne * (ne - 1) * 75                                   # b: the Pade pairs
+    dirs += n_en * ne * 60                                      # e-n parameter: one nucleus
+    dirs += 7 * n_een * ne * ((ne - 1) * na * 120 + na * 20)    # e-e-n parameter: one term
+    if n_en or n_een:                                           # nuclear coordinate: one nucleus
+        dirs += 3 * na * ne * ((60 if n_en else 0) + (ne - 1) * n_een * 120 + n_een * 20)
+    f["jastrow_dirs"] = dirs
     f["total"] = sum(f.values())
     return f
 
@@ -380,7 +406,7 @@ def grad_bench(args, dev) -> dict:
     return {"workload": f"Li2, {W} walkers, d log|Psi|/d theta, d E_L/d theta ({P} parameters), "
                         "d log|Psi|/d R, d E_L/d R",
             "ms_per_call": ms, "walker_gradients_per_s": W / (ms * 1e-3), "dtype": "f64",
-            "flops_per_walker_estimate": fl["total"], "hbm_bytes_per_call": out_bytes,
+            "flops_per_walker": fl["total"], "flops_per_walker_terms": fl, "hbm_bytes_per_call": out_bytes,
             "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                          "hbm_GBps": out_bytes / (ms * 1e-3) / 1e9}}

@@ -556,6 +556,11 @@ __device__ __forceinline__ double value_of(Dual x) { return x.v; }
 
 struct PlainPrm {
     const DevSystem &S;
+    // which terms to evaluate (all of them)
+    __device__ bool use_pade() const { return true; }
+    __device__ bool use_en(int) const { return true; }
+    __device__ bool use_een_term(int) const { return true; }
+    __device__ bool use_een(int, int) const { return true; }  // term m, nucleus a
     __device__ double b() const { return S.b; }
     __device__ double R(int a, int k) const { return S.atoms[4 * a + k]; }
     __device__ double en(int a, int k) const { return S.jas_en[3 * a + k]; }
@@ -567,6 +572,12 @@ struct PlainPrm {
 struct SeedPrm {
     const DevSystem &S;
     int kind, i, k;
+    // only the terms that depend on the seeded entry (the others have zero
+    // derivative)
+    __device__ bool use_pade() const { return kind == 0; }
+    __device__ bool use_en(int a) const { return (kind == 1 || kind == 3) && a == i; }
+    __device__ bool use_een_term(int m) const { return (kind == 2 && m == i) || kind == 3; }
+    __device__ bool use_een(int m, int a) const { return (kind == 2 && m == i) || (kind == 3 && a == i); }
     __device__ Dual b() const { return Dual(S.b, kind == 0 ? 1.0 : 0.0); }
     __device__ Dual R(int a, int kk) const { return Dual(S.atoms[4 * a + kk], (kind == 3 && a == i && kk == k) ? 1.0 : 0.0); }
     __device__ Dual en(int a, int kk) const { return Dual(S.jas_en[3 * a + kk], (kind == 1 && a == i && kk == k) ? 1.0 : 0.0); }
@@ -607,7 +618,8 @@ struct JasTerms {
 // e-e-n kernels of the many-body appendix) of the lane's electron: its share
 // of J, grad_e J and lap_e J; with T = double also its Coulomb terms
 // (eq. Hmol: half of each e-e pair, the e-n attraction).  sPos holds the
-// walker's positions, sF / sG the e-e-n tables of een_table_fill.
+// walker's positions, sF / sG the e-e-n tables of een_table_fill.  A seeded
+// accessor skips the terms that do not depend on its entry.
 template <typename T, typename Prm>
 __device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const Lane &L, double x0, double x1,
                                                      double x2, const double *sPos, const T *sF, const T *sG,
@@ -622,7 +634,7 @@ __device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const L
     o.vpot = 0.0;
     if (!L.active) return o;
     const T b = prm.b();
-    for (int j = 0; j < S.ne; ++j) {
+    for (int j = 0; j < S.ne && prm.use_pade(); ++j) {
         if (j == L.e) continue;
         const int lj = j < S.n_up ? j : S.G + (j - S.n_up);
         const double d0 = x0 - sPos[3 * lj], d1 = x1 - sPos[3 * lj + 1], d2 = x2 - sPos[3 * lj + 2];
@@ -645,7 +657,7 @@ __device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const L
     for (int a = 0; a < S.n_atoms; ++a) {
         const T d0 = x0 - prm.R(a, 0), d1 = x1 - prm.R(a, 1), d2 = x2 - prm.R(a, 2);
         if constexpr (kPlain) o.vpot -= S.atoms[4 * a + 3] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        if (S.jas_en) {
+        if (S.jas_en && prm.use_en(a)) {
             // e-n kernel K = N / D, N = w0 r + w1 r^2, D = 1 + w2 r:
             // K' = (N' - K D') / D and K'' = (N'' - 2 K' D') / D
             const T r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
@@ -675,12 +687,14 @@ __device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const L
         const double rinv = 1.0 / r;
         const double w0 = d0 * rinv, w1 = d1 * rinv, w2 = d2 * rinv;
         for (int m = 0; m < S.een_n; ++m) {
+            if (!prm.use_een_term(m)) continue;
             const T a3 = prm.een(m, 5), b3 = prm.een(m, 6);
             const T q3 = rcp_ge1(1.0 + b3 * r);
             const T f3 = a3 * r * q3, f31 = a3 * q3 * q3, f32 = -2.0 * b3 * f31 * q3;
             const T ao = first ? prm.een(m, 1) : prm.een(m, 3), bo = first ? prm.een(m, 2) : prm.een(m, 4);
             const T cm = prm.een(m, 0);
             for (int a = 0; a < S.n_atoms; ++a) {
+                if (!prm.use_een(m, a)) continue;
                 const T *g = sG + (L.lw * S.n_atoms + a) * 4;
                 const T u = g[0];
                 const T qo = rcp_ge1(1.0 + bo * u);
