@@ -18,7 +18,7 @@ hipError_t launch_eval_fd(const DevSystem &S, const double *X, int64_t W, double
                           hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
     QMC_NMO_SWITCH(hipLaunchKernelGGL((k_eval_fd<N>), dim3((unsigned)blocks), dim3(kWave),
-                                      (size_t)S.WPW * walker_lds<N>(S) * sizeof(double), st, S, X, W, h, LP, EL);
+                                      (size_t)S.WPW * (walker_lds<N, false>(S)) * sizeof(double), st, S, X, W, h, LP, EL);
                    return hipGetLastError())
 }
 

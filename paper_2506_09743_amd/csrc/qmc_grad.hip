@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
 
     // ---- shared stages: MO values, Gauss-Jordan, determinants, a_e ----------
     Core<NMO> c;
-    core_stages<NMO, double>(S, L, wsm, x0, x1, x2, c);
+    core_stages<NMO, double, 0, false, false, false, true>(S, L, wsm, x0, x1, x2, c);
     const double gJ[3] = {c.gJ0, c.gJ1, c.gJ2};
     const double *Tg = sT + L.grp * ts;
     const double *Cg = sC + L.grp * ts;

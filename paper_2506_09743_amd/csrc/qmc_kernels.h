@@ -95,21 +95,32 @@ __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const La
     return res;
 }
 
-template <int NMO, bool EXPL, bool BF>
+template <int NMO, typename RT, bool EXPL, bool BF>
 __host__ __device__ inline int lds_per_walker(const DevSystem &S) {
     if constexpr (BF) return walker_lds_bf<NMO, !EXPL>(S);
     else if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
-    else return walker_lds<NMO>(S);
+    else return walker_lds<NMO, (sizeof(RT) != sizeof(double))>(S);
 }
 
-// Waves per SIMD the kernels ask the compiler for.  LDS (about 18 KB per CO
-// wave) allows two; the register file then allows 256 registers per lane.
-// The FP64 and BF16 Metropolis kernels need the bound to stay within that
-// (left alone they take a few more and run at one wave); the FP32 one fits by
-// itself and runs faster with the registers it chooses.  The explicit and
-// backflow kernels need more LDS or registers per wave and run at one.
-template <int MF, bool EXPL, bool BF, bool MIXED>
-constexpr int metro_waves() { return (EXPL || BF) ? 1 : ((MIXED && MF == 0) ? 1 : 2); }
+// Launch shapes of the Metropolis kernel.  The FP64 low-rank form takes one
+// step per launch (the host enqueues the block step by step; the arrays
+// carry the state between launches): without a step loop the evaluation
+// keeps the registers it has on its own instead of sharing them with values
+// held across steps, and fits three waves per SIMD (168 registers), which
+// its compact LDS tables (about 11.6 KB per CO wave) also allow.  The mixed
+// forms carry both orbital paths and run at two waves; they keep the whole
+// block in one launch (one step per launch measured 1.4x slower for them):
+// the BF16 ones with a two-wave bound (left alone they take a few registers
+// more and run at one), the FP32 one with the registers it chooses (252).
+// The explicit kernel runs the block in one launch at one wave (its LDS and
+// registers), the backflow kernels one step per launch at one wave.
+template <typename RT, int MF, bool EXPL, bool BF>
+constexpr bool metro_one_step() { return BF || (!EXPL && sizeof(RT) == sizeof(double)); }
+
+template <typename RT, int MF, bool EXPL, bool BF>
+constexpr int metro_waves() {
+    return (EXPL || BF) ? 1 : (sizeof(RT) == sizeof(double) ? 3 : (MF == 0 ? 1 : 2));
+}
 
 template <int NMO, typename RT, int MF, bool EXPL, bool BF>
 __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, c
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL, BF>(S);
+    double *wsm = smem + L.wloc * lds_per_walker<NMO, RT, EXPL, BF>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, c
 }
 
 template <int NMO, typename RT, int MF, bool EXPL, bool BF>
-__global__ __launch_bounds__(kWave, (metro_waves<MF, EXPL, BF, sizeof(RT) != sizeof(double)>())) void k_metropolis(DevSystem S, double *__restrict__ X,
+__global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_metropolis(DevSystem S, double *__restrict__ X,
                                                       double *__restrict__ LP, double *__restrict__ SG,
                                                       double *__restrict__ EL, int64_t W, int n_steps,
                                                       double sigma, uint64_t seed, uint64_t step0,
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(kWave, (metro_waves<MF, EXPL, BF, sizeof(RT) != siz
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * lds_per_walker<NMO, EXPL, BF>(S);
+    double *wsm = smem + L.wloc * lds_per_walker<NMO, RT, EXPL, BF>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -172,10 +183,10 @@ __global__ __launch_bounds__(kWave, (metro_waves<MF, EXPL, BF, sizeof(RT) != siz
     const uint32_t wid = walker_offset + (uint32_t)w;
     const double s32 = 1.0 / 4294967296.0;
     const double two_pi = 6.283185307179586;
-    // With backflow every launch takes one step (the host launches the
-    // block step by step): without a loop around it the evaluation keeps
-    // the registers it has on its own.
-    const int steps = BF ? 1 : n_steps;
+    // One step per launch where the host enqueues the block step by step:
+    // without a loop around it the evaluation keeps the registers it has on
+    // its own.
+    const int steps = metro_one_step<RT, MF, EXPL, BF>() ? 1 : n_steps;
     for (int t = 0; t < steps; ++t) {
         const uint64_t step = step0 + (uint64_t)t;
         uint32_t c[4] = {wid, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)L.e};
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(kWave, 1) void k_eval_fd(DevSystem S, const double 
     extern __shared__ double smem[];
     int64_t w;
     const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
-    double *wsm = smem + L.wloc * walker_lds<NMO>(S);
+    double *wsm = smem + L.wloc * walker_lds<NMO, false>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
         const double *p = X + (w * S.ne + L.e) * 3;
@@ -292,10 +303,10 @@ static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, d
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
                            uint32_t woff, double *ACC, hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
-    const int per = BF ? walker_lds_bf<NMO, !EXPL>(S) : (EXPL ? walker_lds_explicit<NMO>(S) : walker_lds<NMO>(S));
+    const int per = lds_per_walker<NMO, RT, EXPL, BF>(S);
     size_t lds = (size_t)S.WPW * per * sizeof(double);
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
-    if (mc && BF) {
+    if (mc && metro_one_step<RT, MF, EXPL, BF>()) {
         // one launch per step; the state and the running sums go through
         // the caller's arrays between launches, so the result is the block's
         for (int t = 0; t < n_steps; ++t) {

@@ -167,15 +167,15 @@ __device__ __forceinline__ double ratio(const double *T, const int *d) {
 }
 
 // Determinant ratio from a packed excitation code (rank | h1 << 2 |
-// h2 << 5 | p1 << 8 | p2 << 13).
-template <int NMO>
-__device__ __forceinline__ double ratio_code(const double *T, uint32_t c) {
+// h2 << 5 | p1 << 8 | p2 << 13); T rows of `ts` columns starting at column
+// c0 (particles are virtual orbitals, p >= c0).
+__device__ __forceinline__ double ratio_code(const double *T, uint32_t c, int ts, int c0) {
     const uint32_t k = c & 3u;
     if (k == 0) return 1.0;
-    const int h1 = (c >> 2) & 7, h2 = (c >> 5) & 7, p1 = (c >> 8) & 31, p2 = (c >> 13) & 31;
-    const double a = T[h1 * NMO + p1];
+    const int h1 = (c >> 2) & 7, h2 = (c >> 5) & 7, p1 = ((c >> 8) & 31) - c0, p2 = ((c >> 13) & 31) - c0;
+    const double a = T[h1 * ts + p1];
     if (k == 1) return a;
-    return a * T[h2 * NMO + p2] - T[h1 * NMO + p2] * T[h2 * NMO + p1];
+    return a * T[h2 * ts + p2] - T[h1 * ts + p2] * T[h2 * ts + p1];
 }
 
 // d = a * b + c as one three-address FMA: the constant c stays in the
@@ -485,27 +485,49 @@ __device__ __forceinline__ void mo_values_mfma(const DevSystem &S, int lane, voi
     __syncthreads();
 }
 
-// LDS of one walker (doubles): T tables [2][nmax][NMO] at 0 (nmax =
-// max(n_up, n_dn)) and the cofactor tables [2][nmax][NMO] after them, both
-// written from the determinant stage on.  Before it the same space holds
-// the e-e-n factor table (een_table doubles at 0, when e-e-n terms exist)
-// and the positions [LW][3] + pivot rows [2][NMO] at pos_offset.
+// LDS of one walker (doubles): T tables [2][nmax][cols] at 0 (nmax =
+// max(n_up, n_dn)) and the cofactor tables [2][nmax][cregion] after them,
+// both written from the determinant stage on.  FULL layout (the adjoint's):
+// cols = NMO, the T rows holding A0^-1 in their reference columns.  Compact
+// layout (the evaluation and Metropolis kernels'): only the columns from
+// c0 = min(n_up, n_dn) on, the ones the ratios and cofactors read; A0^-1
+// passes through the cofactor region (cregion = max(cols, nmax) per row)
+// before the cofactors accumulate there.  Before the determinant stage the
+// same space holds the e-e-n factor table (een_table doubles at 0, when
+// e-e-n terms exist) and the positions [LW][3] + pivot rows [2][NMO] at
+// pos_offset.
 __host__ __device__ inline int een_table(const DevSystem &S) {
     return S.een_n > 0 ? S.LW * S.n_atoms * (2 * S.een_n + 4) : 0;
 }
 
-template <int NMO>
+template <int NMO, bool FULL = true>
+__host__ __device__ inline int tab_c0(const DevSystem &S) {
+    return FULL ? 0 : (S.n_up < S.n_dn ? S.n_up : S.n_dn);
+}
+
+template <int NMO, bool FULL = true>
+__host__ __device__ inline int tab_cols(const DevSystem &S) {
+    return NMO - tab_c0<NMO, FULL>(S);
+}
+
+template <int NMO, bool FULL = true>
+__host__ __device__ inline int tab_cregion(const DevSystem &S) {
+    const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn, cols = tab_cols<NMO, FULL>(S);
+    return FULL ? cols : (cols > nmax ? cols : nmax);
+}
+
+template <int NMO, bool FULL = true>
 __host__ __device__ inline int pos_offset(const DevSystem &S) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
-    const int t = 2 * nmax * NMO, f = een_table(S);
+    const int t = 2 * nmax * tab_cols<NMO, FULL>(S), f = een_table(S);
     return f > t ? f : t;
 }
 
-template <int NMO>
+template <int NMO, bool FULL = true>
 __host__ __device__ inline int walker_lds(const DevSystem &S) {
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
-    const int tc = 4 * nmax * NMO;
-    const int pp = pos_offset<NMO>(S) + 3 * S.LW + 2 * NMO;
+    const int tc = 2 * nmax * (tab_cols<NMO, FULL>(S) + tab_cregion<NMO, FULL>(S));
+    const int pp = pos_offset<NMO, FULL>(S) + 3 * S.LW + 2 * NMO;
     return tc > pp ? tc : pp;
 }
 
@@ -746,16 +768,24 @@ __host__ __device__ inline int bf_pos_offset(const DevSystem &S);
 // the values a finite-difference kinetic energy needs.  RT is the arithmetic
 // of the AO evaluation and MF the MO contraction of pass 1 (FP64 when RT is
 // double); hi (wave-uniform) switches a mixed form to the FP64 AO/MO path.
-template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false, bool PSI = false>
+// FULLT: the full table layout (walker_lds<NMO, true>), which the adjoint
+// reads; otherwise the compact one.
+template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false, bool PSI = false,
+          bool FULLT = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
                                             double &x1, double &x2, Core<NMO> &c, void *stage = nullptr,
                                             bool hi = false) {
+    // the compact layout serves the FP64 low-rank kernels (three waves per
+    // SIMD); the mixed forms run at two waves either way
+    constexpr bool kFull = FULLT || EXPL || BF || sizeof(RT) != sizeof(double);
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
-    const int tstride = nmax * NMO;          // doubles per spin table
-    double *sT = wsm;                        // [2][nmax][NMO]
-    double *sC = sT + 2 * tstride;           // [2][nmax][NMO] after the elimination
+    const int c0 = tab_c0<NMO, kFull>(S), ts = tab_cols<NMO, kFull>(S);
+    const int tstride = nmax * ts;                           // doubles per spin T table
+    const int cstride = nmax * tab_cregion<NMO, kFull>(S);   // doubles per spin cofactor table
+    double *sT = wsm;                        // [2][nmax][ts]
+    double *sC = sT + 2 * tstride;           // [2][nmax][cregion / nmax] after the elimination
     // [LW][3] before the elimination (with backflow: after the backflow tables)
-    double *sPos = wsm + (BF ? bf_pos_offset<NMO, !EXPL>(S) : pos_offset<NMO>(S));
+    double *sPos = wsm + (BF ? bf_pos_offset<NMO, !EXPL>(S) : pos_offset<NMO, kFull>(S));
     double *sPiv = sPos + 3 * S.LW;          // [2][NMO] during it
     // e-e-n table before the elimination: per lane [n_atoms][een_n][2]
     // factor values (f1, f2) of its electron, then [n_atoms][4] geometry
@@ -763,7 +793,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     double *sF = wsm;
     double *sG = wsm + S.LW * S.n_atoms * 2 * S.een_n;
     double *Tg = sT + L.grp * tstride;
-    double *Cg = sC + L.grp * tstride;
+    double *Cg = sC + L.grp * cstride;
     double *piv_row = sPiv + L.grp * NMO;
 
     if (!L.active) {  // a far point keeps idle lanes finite
@@ -864,9 +894,25 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         }
         __syncthreads();
     }
+    // compact layout: the reference part of each slot's row (A0^-1) goes
+    // to the cofactor region for a moment, and each lane keeps its column
+    double ainv[JMAX];
     if (L.active && slot >= 0) {
 #pragma unroll
-        for (int m = 0; m < NMO; ++m) Tg[slot * NMO + m] = a[m];
+        for (int m = 0; m < NMO; ++m)
+            if (m >= c0) Tg[slot * ts + m - c0] = a[m];
+        if constexpr (!kFull) {
+#pragma unroll
+            for (int k = 0; k < JMAX; ++k)
+                if (k < L.nsig) Cg[slot * nmax + k] = a[k];
+        }
+    }
+    if constexpr (!kFull) {
+        __syncthreads();
+        const int sl = slot < 0 ? 0 : slot;
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) ainv[k] = (k < nmax && k < L.nsig && L.active) ? Cg[k * nmax + sl] : 0.0;
+        __syncthreads();
     }
     // Permutation parity (slot s <- electron row): inversions within the group.
     int inv_cnt = 0;
@@ -878,7 +924,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     const double det_sign = ((inv_cnt & 1) ? -1.0 : 1.0) * (dprod < 0.0 ? -1.0 : 1.0);
     const double det_log = log(fabs(dprod));
     // the shared region now becomes the cofactor tables: zero them
-    for (int q = L.lw; q < 2 * tstride; q += S.LW) sC[q] = 0.0;
+    for (int q = L.lw; q < 2 * cstride; q += S.LW) sC[q] = 0.0;
     __syncthreads();
 
     const int wb = L.lane - L.lw;
@@ -898,7 +944,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
 #pragma unroll
         for (int u = 0; u < kRecBatch; ++u) {
             const uint4 r = rb[u];
-            Sp += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(Tup, r.z) * ratio_code<NMO>(Tdn, r.w);
+            Sp += __hiloint2double((int)r.y, (int)r.x) * ratio_code(Tup, r.z, ts, c0) * ratio_code(Tdn, r.w, ts, c0);
         }
     }
     const double Ssum = walker_sum(Sp, S.LW);
@@ -930,11 +976,11 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
                 const int spin = (r.w >> 1) & 1;
                 const double *Ts = spin ? Tdn : Tup, *To = spin ? Tup : Tdn;
                 const uint32_t cc = r.z >> 18;
-                const double tv = Ts[((cc >> 2) & 7) * NMO + (cc >> 5)];
+                const double tv = Ts[((cc >> 2) & 7) * ts + (cc >> 5) - c0];
                 const double cof = (cc & 3) == 0 ? 1.0 : ((cc & 3) == 1 ? tv : -tv);
-                acc += __hiloint2double((int)r.y, (int)r.x) * ratio_code<NMO>(To, r.z & 0x3FFFFu) * cof;
+                acc += __hiloint2double((int)r.y, (int)r.x) * ratio_code(To, r.z & 0x3FFFFu, ts, c0) * cof;
                 if (r.w & 1u) {
-                    sC[spin * tstride + ((r.w >> 2) & 7) * NMO + (r.w >> 5)] = acc;
+                    sC[spin * cstride + ((r.w >> 2) & 7) * ts + (r.w >> 5) - c0] = acc;
                     acc = 0.0;
                 }
             }
@@ -948,14 +994,15 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     // sum_v T[k][v] a_e[v].
     double (&av)[NMO] = c.av;
     {
-        const int sl = slot < 0 ? 0 : slot;
-        double ainv[JMAX];
+        if constexpr (kFull) {
+            const int sl = slot < 0 ? 0 : slot;
 #pragma unroll
-        for (int k = 0; k < JMAX; ++k) {
-            ainv[k] = 0.0;
-            if (k < nmax) {
-                const double t = Tg[k * NMO + sl];
-                ainv[k] = (k < L.nsig && L.active) ? t : 0.0;
+            for (int k = 0; k < JMAX; ++k) {
+                ainv[k] = 0.0;
+                if (k < nmax) {
+                    const double t = Tg[k * ts + sl];
+                    ainv[k] = (k < L.nsig && L.active) ? t : 0.0;
+                }
             }
         }
         const double Sinv = 1.0 / Ssum;
@@ -965,7 +1012,8 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
         for (int k = 0; k < JMAX; ++k) {
             if (k >= nmax) break;
 #pragma unroll
-            for (int v = 0; v < NMO; ++v) av[v] += ainv[k] * Cg[k * NMO + v];
+            for (int v = 0; v < NMO; ++v)
+                if (v >= c0) av[v] += ainv[k] * Cg[k * ts + v - c0];
         }
 #pragma unroll
         for (int v = 0; v < NMO; ++v) av[v] *= Sinv;
@@ -975,7 +1023,8 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
             h[k] = 0.0;
             if (k < nmax) {
 #pragma unroll
-                for (int v = 0; v < NMO; ++v) h[k] += Tg[k * NMO + v] * av[v];
+                for (int v = 0; v < NMO; ++v)
+                    if (v >= c0) h[k] += Tg[k * ts + v - c0] * av[v];
             }
         }
 #pragma unroll

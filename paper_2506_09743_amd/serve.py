@@ -179,6 +179,9 @@ class Server:
         if self._free_streams is None:
             self._free_streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_active)]
         while True:
+            # read before draining the queue: once the producer has ended,
+            # everything it submitted is in the queue when it is drained
+            producer_done = producer is None or not producer.is_alive()
             self._drain_queue()
             self._admit()
             self._launch()
@@ -186,7 +189,7 @@ class Server:
             idle = not self.active and not self.pending and self.q.empty()
             if idle or len(self._retired_systems) > 64:
                 self._destroy_retired()
-            if idle and stop_when_idle and (producer is None or not producer.is_alive()):
+            if idle and stop_when_idle and producer_done:
                 break
             if not retired:
                 time.sleep(poll_s)
