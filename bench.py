@@ -598,9 +598,13 @@ def backflow_bench(args, dev, seed) -> dict:
             "sd_sweep_1000_walkers": sweep}
 
 
-def summarize_trace(path: str, kernel_regex: str, skip: int) -> dict:
+def summarize_trace(path: str, kernel_regex: str, skip: int, block: int = 0) -> dict:
     """Durations of one kernel's dispatches in a rocprofv3 kernel-trace CSV,
-    leaving out its first `skip` dispatches (burn-in and warm-up launches)."""
+    leaving out its first `skip` dispatches (burn-in and warm-up launches).
+    block > 0: the remaining dispatches, in start order, form consecutive
+    groups of `block` (one qmc_metropolis_block call: its step launches, two
+    per step when the walkers run in two halves on two streams), and the
+    span of each group (first start to last end) is reported too."""
     import csv
     import re
     pat = re.compile(kernel_regex)
@@ -608,12 +612,19 @@ def summarize_trace(path: str, kernel_regex: str, skip: int) -> dict:
     with open(path, newline="") as f:
         for r in csv.DictReader(f):
             if pat.search(r["Kernel_Name"]):
-                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
     rows.sort()
-    d = np.array([x[1] for x in rows[skip:]], dtype=np.float64)
-    return {"kernel_regex": kernel_regex, "dispatches_total": len(rows), "skipped": skip,
-            "dispatches": int(d.size), "mean_ns": float(d.mean()), "median_ns": float(np.median(d)),
-            "min_ns": float(d.min()), "max_ns": float(d.max())}
+    rows = rows[skip:]
+    d = np.array([e - s for s, e in rows], dtype=np.float64)
+    out = {"kernel_regex": kernel_regex, "dispatches_total": len(rows) + skip, "skipped": skip,
+           "dispatches": int(d.size), "mean_ns": float(d.mean()), "median_ns": float(np.median(d)),
+           "min_ns": float(d.min()), "max_ns": float(d.max())}
+    if block > 0:
+        spans = [max(e for _, e in rows[i:i + block]) - rows[i][0]
+                 for i in range(0, len(rows) - block + 1, block)]
+        out.update(dispatches_per_block=block, blocks=len(spans), block_span_mean_ns=float(np.mean(spans)),
+                   block_span_median_ns=float(np.median(spans)))
+    return out
 
 
 def main():
@@ -646,9 +657,12 @@ def main():
                          "kernel-trace CSV (no GPU run)")
     ap.add_argument("--trace-kernel", default=r"k_metropolis<20, double, 0, false, false>")
     ap.add_argument("--trace-skip", type=int, default=0, help="leading dispatches to leave out")
+    ap.add_argument("--trace-block", type=int, default=0,
+                    help="dispatches per qmc_metropolis_block call (block spans; 0: none)")
     args = ap.parse_args()
     if args.summarize_trace:
-        print(json.dumps(summarize_trace(args.summarize_trace, args.trace_kernel, args.trace_skip)))
+        print(json.dumps(summarize_trace(args.summarize_trace, args.trace_kernel, args.trace_skip,
+                                         args.trace_block)))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the walkers of a multi-GPU run would be independent "
@@ -782,6 +796,8 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
                 "kernel": "k_metropolis<20,double> (qmc_metropolis_block)",
+                "launch": (f"one qmc_metropolis_block call of {args.chunk} steps: one k_metropolis dispatch "
+                           "per step and half of the walkers, the halves on two streams"),
                 "flops_per_walker_step": per_unit, "flops_per_walker_step_recount": fl["total"],
                 "walker_steps_per_launch": W * args.chunk,
                 "hbm_bytes_per_launch_algorithmic": hbm_bytes_per_launch(sysd, W),

@@ -25,8 +25,13 @@
  *     descriptor are copied at create and may be freed afterwards.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
  *     call is asynchronous on that stream; results are valid once the stream
- *     has been synchronised.
- *   - One handle is used from one host thread at a time.
+ *     has been synchronised.  Some Metropolis blocks also use a second
+ *     stream owned by the handle, forked from and joined back to `stream`
+ *     with events inside the call, so the ordering seen by the caller is
+ *     that of `stream` alone.
+ *   - Calls on one handle from several host threads are serialised while
+ *     they enqueue (a mutex in the handle); their device work follows the
+ *     streams they were given.
  *   - No call aborts, throws or prints.  Argument checks run before any
  *     launch and return QMC_EINVAL (QMC_ENONFINITE for a NaN or infinite
  *     value where a finite one is required); an unsupported shape returns
@@ -75,7 +80,14 @@ typedef enum {
    finite or exceeds 3e4 Ha in magnitude is evaluated again with FP64
    orbitals (those are walkers with an electron inside the tightest
    primitives, where cancelling kinetic terms amplify the orbital rounding);
-   its results are then the FP64 form's.
+   its results are then the FP64 form's.  The re-evaluation runs in a later
+   launch of the same call: until the call completes, the walker's sign entry
+   holds a mark (a value >= 4) and the walker is otherwise left as it was,
+   so a mixed-form Metropolis call reads each sign entry as its sign
+   (> 0: +1, < 0: -1, else 0).  In a Metropolis block a walker re-evaluated
+   at some step takes the block's later steps in that later launch (on the
+   handle's second stream, one step behind): the results are those of
+   single-step calls, only the order of work differs.
    The BF16 forms need n_ao <= 32.
    QMC_FP64_EXPLICIT is FP64 with a different determinant method, kept for
    comparison: every distinct spin configuration of the CI expansion is
@@ -179,9 +191,11 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
    steps left out of the sums.  The caller zeroes d_acc before a block's
    first call.  Results depend only on (seed, walker_offset + w, t), never on
    W or on how walkers are batched.  sigma must be finite (QMC_ENONFINITE)
-   and >= 0 (QMC_EINVAL).  With backflow the block is enqueued as one kernel
-   per step on `stream` (the arrays carry the state between them); otherwise
-   as one kernel. */
+   and >= 0 (QMC_EINVAL).  Enqueued as one kernel per step (the arrays carry
+   the state between them; a mixed form adds its re-evaluation kernels on
+   the handle's second stream), except QMC_FP64_EXPLICIT: one kernel.  An
+   FP64 block of at least 1536 waves of walkers runs its walkers in two
+   halves, one on `stream` and one on the second stream. */
 qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X, double *d_logpsi,
                                 double *d_sign, double *d_eloc, int64_t W, int32_t n_steps,
                                 double sigma, uint64_t seed, uint64_t step0,

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -18,7 +19,7 @@
 namespace qmc {
 hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, double *LP, double *SG,
                           double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
-                          uint64_t step0, uint32_t woff, double *ACC, hipStream_t st);
+                          uint64_t step0, uint32_t woff, double *ACC, const CallStreams &cs);
 int padded_mo(int n_mo);
 hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *dlogpsi,
                        double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param,
@@ -39,6 +40,11 @@ struct qmc_system {
     void *d_mem;        // one allocation holding every table
     int n_prim;
     int64_t n_params;
+    // second stream and events of the two-stream launches; the mutex keeps
+    // calls from several host threads from interleaving their use
+    hipStream_t side = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::mutex mu;
 };
 
 namespace {
@@ -546,6 +552,14 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
         (void)hipFree(dm);
         return QMC_ENOMEM;
     }
+    sys->device = device;
+    sys->d_mem = dm;
+    bool made = hipStreamCreateWithFlags(&sys->side, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 4 && made; ++k) made = hipEventCreateWithFlags(&sys->ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!made) {
+        qmc_system_destroy(sys);
+        return QMC_EDEVICE;
+    }
     unsigned char *base = (unsigned char *)dm;
     DevSystem &S = sys->S;
     S.n_up = nu;
@@ -598,8 +612,6 @@ qmc_status qmc_system_create(const qmc_system_desc *d, int32_t device, qmc_syste
     S.cfg_use = (const int2 *)(base + o_cuse);
     S.bf_omega = d->bf_omega;
     S.cfg_exc = (const int *)(base + o_cexc);
-    sys->device = device;
-    sys->d_mem = dm;
     sys->n_prim = (int)prims.size();
     // exponents | MO coefficients | Pade b | e-n (w0, w1, w2) per nucleus | e-e-n 7 per term
     sys->n_params = (int64_t)prims.size() + (int64_t)n_ao * d->n_mo + 1 + (d->jas_en ? 3 * (int64_t)d->n_atoms : 0) +
@@ -612,6 +624,9 @@ void qmc_system_destroy(qmc_system *sys) {
     if (!sys) return;
     {
         DeviceGuard g(sys->device);
+        for (hipEvent_t e : sys->ev)
+            if (e) (void)hipEventDestroy(e);
+        if (sys->side) (void)hipStreamDestroy(sys->side);
         (void)hipFree(sys->d_mem);
     }
     delete sys;
@@ -651,9 +666,10 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
     if (!d_X || !d_logpsi || !d_sign || !d_eloc) return QMC_EINVAL;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
+    std::lock_guard<std::mutex> lock(sys->mu);
+    const qmc::CallStreams cs{(hipStream_t)stream, sys->side, {sys->ev[0], sys->ev[1], sys->ev[2], sys->ev[3]}};
     hipError_t e = qmc::launch_walkers(false, walk_form(sys, precision), sys->S, (double *)d_X,
-                                       d_logpsi, d_sign, d_eloc, W, 0, 0.0, 0, 0, 0, nullptr,
-                                       (hipStream_t)stream);
+                                       d_logpsi, d_sign, d_eloc, W, 0, 0.0, 0, 0, 0, nullptr, cs);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 
@@ -670,9 +686,11 @@ qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X,
     if (!d_X || !d_logpsi || !d_sign || !d_eloc || !d_acc) return QMC_EINVAL;
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
+    std::lock_guard<std::mutex> lock(sys->mu);
+    const qmc::CallStreams cs{(hipStream_t)stream, sys->side, {sys->ev[0], sys->ev[1], sys->ev[2], sys->ev[3]}};
     hipError_t e = qmc::launch_walkers(true, walk_form(sys, precision), sys->S, d_X, d_logpsi,
                                        d_sign, d_eloc, W, n_steps, sigma, seed, step0, walker_offset,
-                                       d_acc, (hipStream_t)stream);
+                                       d_acc, cs);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 

@@ -14,6 +14,14 @@ constexpr int kWave = 64;
 // Ints per determinant record: (rank, h1, h2, p1, p2) for spin up, then down.
 constexpr int kDetInts = 10;
 
+// Streams and events of one walker call: st is the caller's stream; side
+// is a second stream and ev[0..3] events (timing off) owned by the system
+// handle, used by launches that run on two streams.
+struct CallStreams {
+    hipStream_t st, side;
+    hipEvent_t ev[4];
+};
+
 // Everything a kernel needs about one system; passed by value as a kernel
 // argument.  Pointers refer to one device allocation owned by the handle.
 struct DevSystem {

@@ -18,18 +18,21 @@ struct WalkerResult {
 
 // Mixed forms: a walker whose kinetic energy from the FP32 orbitals exceeds
 // this magnitude (Ha), or is not finite, is evaluated again with FP64
-// orbitals.  Such walkers have an electron inside the tightest primitives,
+// orbitals (by the refinement launch that follows every mixed launch).  Such walkers have an electron inside the tightest primitives,
 // where the kinetic terms are 1e4 - 1e6 Ha and cancel, so the rounding of
 // FP32 orbital values (amplified by the Slater inverse) reaches ~1 Ha.
 constexpr double kRefineKinetic = 3.0e4;
 
-// One evaluation of log|Psi|, sign and E_L (hi: FP64 orbitals in a mixed
-// form); kin receives the walker's kinetic energy.
+// Evaluates log|Psi|, sign and E_L of the lane's walker at the electron
+// positions held by its lanes (x0, x1, x2 of the lane's electron).  Every
+// lane of the block must call it (it contains block barriers); results are
+// identical on all lanes of a walker.  need: a mixed form's result must be
+// refined in FP64 (kinetic energy not finite or above kRefineKinetic).
 template <int NMO, typename RT, int MF, bool EXPL, bool BF>
-__device__ __forceinline__ WalkerResult eval_once(const DevSystem &S, const Lane &L, double *wsm, double x0,
-                                                  double x1, double x2, void *stage, bool hi, double &kin_w) {
+__device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
+                                                    double x1, double x2, void *stage, bool &need) {
     Core<NMO> c;
-    core_stages<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, c, stage, hi);
+    core_stages<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, c, stage);
 
     // ---- pass 2: grad and Laplacian of Sigma at this electron ---------------
     double gS0, gS1, gS2, lapS;
@@ -40,8 +43,6 @@ __device__ __forceinline__ WalkerResult eval_once(const DevSystem &S, const Lane
         gS1 = c.bgS1;
         gS2 = c.bgS2;
         lapS = c.blap;
-    } else if (sizeof(RT) == sizeof(double) || hi) {
-        sigma_derivs<NMO, double>(S, x0, x1, x2, c.av, gS0, gS1, gS2, lapS);
     } else {
         sigma_derivs<NMO, RT>(S, x0, x1, x2, c.av, gS0, gS1, gS2, lapS);
     }
@@ -55,7 +56,8 @@ __device__ __forceinline__ WalkerResult eval_once(const DevSystem &S, const Lane
     }
     const double eloc = walker_sum(part, S.LW) + S.vnn;
     const double Jw = walker_sum(c.J, S.LW);
-    kin_w = walker_sum(kin, S.LW);
+    need = false;
+    if constexpr (sizeof(RT) != sizeof(double)) need = L.wvalid && !(fabs(walker_sum(kin, S.LW)) <= kRefineKinetic);
     WalkerResult res;
     if (c.sing_walker > 0 || c.Ssum == 0.0 || !L.wvalid) {
         res.logpsi = -INFINITY;
@@ -70,65 +72,61 @@ __device__ __forceinline__ WalkerResult eval_once(const DevSystem &S, const Lane
     return res;
 }
 
-// Evaluates log|Psi|, sign and E_L of the lane's walker at the electron
-// positions held by its lanes (x0, x1, x2 of the lane's electron).  Every
-// lane of the block must call it (it contains block barriers); results are
-// identical on all lanes of a walker.  In the mixed forms a second pass
-// with FP64 orbitals runs when a walker of the wave needs it (wave-uniform
-// branch); only the walkers that need it take its results, so a walker's
-// result still depends on its own positions only.
-template <int NMO, typename RT, int MF, bool EXPL, bool BF>
-__device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
-                                                    double x1, double x2, void *stage) {
-    constexpr bool kMixed = sizeof(RT) != sizeof(double);
-    WalkerResult res;
-    bool need = false;
-#pragma unroll 1
-    for (int pass = 0; pass < (kMixed ? 2 : 1); ++pass) {
-        double kin_w;
-        const WalkerResult r = eval_once<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, stage, pass > 0, kin_w);
-        if (pass == 0 || need) res = r;
-        if (pass > 0) break;
-        need = L.wvalid && !(fabs(kin_w) <= kRefineKinetic);
-        if (!kMixed || !__any(need ? 1 : 0)) break;
-    }
-    return res;
-}
-
 template <int NMO, typename RT, bool EXPL, bool BF>
 __host__ __device__ inline int lds_per_walker(const DevSystem &S) {
     if constexpr (BF) return walker_lds_bf<NMO, !EXPL>(S);
     else if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
-    else return walker_lds<NMO, (sizeof(RT) != sizeof(double))>(S);
+    else return walker_lds<NMO, false>(S);
 }
 
-// Launch shapes of the Metropolis kernel.  The FP64 low-rank form takes one
-// step per launch (the host enqueues the block step by step; the arrays
-// carry the state between launches): without a step loop the evaluation
-// keeps the registers it has on its own instead of sharing them with values
-// held across steps, and fits three waves per SIMD (168 registers), which
-// its compact LDS tables (about 11.6 KB per CO wave) also allow.  The mixed
-// forms carry both orbital paths and run at two waves; they keep the whole
-// block in one launch (one step per launch measured 1.4x slower for them):
-// the BF16 ones with a two-wave bound (left alone they take a few registers
-// more and run at one), the FP32 one with the registers it chooses (252).
-// The explicit kernel runs the block in one launch at one wave (its LDS and
-// registers), the backflow kernels one step per launch at one wave.
+// Launch shapes of the Metropolis kernel.  The low-rank forms take one step
+// per launch (the host enqueues the block step by step; the arrays carry
+// the state between launches): without a step loop the evaluation keeps the
+// registers it has on its own instead of sharing them with values held
+// across steps, and the FP64 and FP32 kernels fit three waves per SIMD (168
+// registers), which their compact LDS tables (about 11.6 KB per CO wave)
+// also allow.  The BF16 kernels stage operands in about 19 KB of LDS per
+// wave and run at two.  The explicit kernel runs the block in one launch at
+// one wave (its LDS and registers), the backflow kernels one step per launch
+// at one wave.
 template <typename RT, int MF, bool EXPL, bool BF>
-constexpr bool metro_one_step() { return BF || (!EXPL && sizeof(RT) == sizeof(double)); }
+constexpr bool metro_one_step() { return BF || !EXPL; }
 
 template <typename RT, int MF, bool EXPL, bool BF>
-constexpr int metro_waves() {
-    return (EXPL || BF) ? 1 : (sizeof(RT) == sizeof(double) ? 3 : (MF == 0 ? 1 : 2));
+constexpr int metro_waves() { return (EXPL || BF) ? 1 : (MF == 0 ? 3 : 2); }
+
+// Refinement of the mixed forms.  A walker whose FP32 result needs FP64
+// orbitals is left as it was and marked in its sign entry: sign + mark, a
+// sign being -1, 0 or +1 and a mark a multiple of 8 (>= 8).  The mark holds
+// a kind and the step it refers to (mod 4):
+//   deferred  (kind 0): step s was tried in FP32 and must be redone in FP64;
+//   lagging   (kind 1): step s is still to be taken.
+// An evaluation only defers (k_refine redoes the marked walkers).  In a
+// Metropolis block, the step kernels skip marked walkers and k_refine, on a
+// second stream one step behind, takes the marked ones: the deferred step
+// in FP64, then each later step of the call in FP32 with FP64 where that
+// needs it, so those walkers stay off the step kernels' critical path for
+// the rest of the call and the last step leaves them unmarked.  No memory
+// beyond the caller's arrays is used.
+constexpr double kMarkUnit = 8.0;
+
+__device__ __forceinline__ bool marked(double sg) { return sg >= 0.5 * kMarkUnit; }
+
+__device__ __forceinline__ double mark_of(int kind, uint64_t step) {
+    return kMarkUnit * (double)(1 + (int)(step & 3u) + 4 * kind);
 }
 
+// code of a marked entry: (step & 3) | kind << 2; its sign is what is left
+__device__ __forceinline__ int mark_code(double sg) { return (int)rint(sg / kMarkUnit) - 1; }
+
+// One evaluation of the walkers of a wave (w: this lane's walker).  A mixed
+// form defers the walkers to refine (their log|Psi| and E_L are left
+// unwritten); the refinement evaluates them again in FP64.
 template <int NMO, typename RT, int MF, bool EXPL, bool BF>
-__global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
-                                                 double *__restrict__ LP, double *__restrict__ SG,
-                                                 double *__restrict__ EL) {
-    extern __shared__ double smem[];
-    int64_t w;
-    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+__device__ __forceinline__ void eval_wave(const DevSystem &S, const Lane &L, int64_t w, const double *__restrict__ X,
+                                          double *__restrict__ LP, double *__restrict__ SG,
+                                          double *__restrict__ EL, double *smem) {
+    constexpr bool kMixed = sizeof(RT) != sizeof(double);
     double *wsm = smem + L.wloc * lds_per_walker<NMO, RT, EXPL, BF>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
@@ -137,23 +135,37 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, c
         x1 = p[1];
         x2 = p[2];
     }
-    const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, smem);
+    bool need;
+    const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, x0, x1, x2, smem, need);
     if (L.wvalid && L.lw == 0) {
-        LP[w] = r.logpsi;
-        SG[w] = r.sign;
-        EL[w] = r.eloc;
+        if (kMixed && need) {
+            SG[w] = mark_of(0, 0);
+        } else {
+            LP[w] = r.logpsi;
+            SG[w] = r.sign;
+            EL[w] = r.eloc;
+        }
     }
 }
 
+// Marks of one Metropolis step: in_mark is subtracted from the sign read
+// (the walker's current mark, 0 when unmarked); a completed step stores
+// sign + done_mark, a mixed step that needs FP64 stores sign + defer_mark
+// and leaves the walker untouched.
+struct StepMarks {
+    double in_mark, done_mark, defer_mark;
+};
+
+// n_steps Metropolis steps of the valid walkers of a wave (w: this lane's
+// walker).  Mixed forms take one step per call and read a caller's sign
+// entry as its sign.
 template <int NMO, typename RT, int MF, bool EXPL, bool BF>
-__global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_metropolis(DevSystem S, double *__restrict__ X,
-                                                      double *__restrict__ LP, double *__restrict__ SG,
-                                                      double *__restrict__ EL, int64_t W, int n_steps,
-                                                      double sigma, uint64_t seed, uint64_t step0,
-                                                      uint32_t walker_offset, double *__restrict__ ACC) {
-    extern __shared__ double smem[];
-    int64_t w;
-    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+__device__ __forceinline__ void metropolis_wave(const DevSystem &S, const Lane &L, int64_t w, double *__restrict__ X,
+                                                double *__restrict__ LP, double *__restrict__ SG,
+                                                double *__restrict__ EL, int n_steps, double sigma, uint64_t seed,
+                                                uint64_t step0, uint32_t walker_offset, double *__restrict__ ACC,
+                                                double *smem, StepMarks mk) {
+    constexpr bool kMixed = sizeof(RT) != sizeof(double);
     double *wsm = smem + L.wloc * lds_per_walker<NMO, RT, EXPL, BF>(S);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (L.active) {
@@ -165,8 +177,9 @@ __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_me
     double lp = 0.0, sg = 0.0, el = 0.0;
     if (L.wvalid) {
         lp = LP[w];
-        sg = SG[w];
+        sg = SG[w] - mk.in_mark;
         el = EL[w];
+        if constexpr (kMixed) sg = sg > 0.0 ? 1.0 : (sg < 0.0 ? -1.0 : 0.0);
     }
     // running accumulators start from the caller's values, so a block split
     // at any step gives the same sums as one block
@@ -183,11 +196,8 @@ __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_me
     const uint32_t wid = walker_offset + (uint32_t)w;
     const double s32 = 1.0 / 4294967296.0;
     const double two_pi = 6.283185307179586;
-    // One step per launch where the host enqueues the block step by step:
-    // without a loop around it the evaluation keeps the registers it has on
-    // its own.
-    const int steps = metro_one_step<RT, MF, EXPL, BF>() ? 1 : n_steps;
-    for (int t = 0; t < steps; ++t) {
+    bool defer = false;
+    for (int t = 0; t < n_steps; ++t) {
         const uint64_t step = step0 + (uint64_t)t;
         uint32_t c[4] = {wid, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)L.e};
         philox4x32_10(c, k0, k1);
@@ -207,7 +217,10 @@ __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_me
         const uint64_t bits = ((((uint64_t)ca[0]) << 32) | (uint64_t)ca[1]) >> 11;
         const double u = (double)bits * (1.0 / 9007199254740992.0);
 
-        const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, y0, y1, y2, smem);
+        bool need;
+        const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, y0, y1, y2, smem, need);
+        defer = kMixed && need;
+        if (defer) continue;  // one step per call in the mixed forms
         const bool acc = isfinite(r.logpsi) && (u < exp(2.0 * (r.logpsi - lp)));
         if (acc) {
             x0 = y0;
@@ -226,6 +239,10 @@ __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_me
         }
         n_acc += acc ? 1 : 0;
     }
+    if (defer) {  // state unchanged, sign marked
+        if (L.wvalid && L.lw == 0) SG[w] = sg + mk.defer_mark;
+        return;
+    }
     if (L.active) {
         double *p = X + (w * S.ne + L.e) * 3;
         p[0] = x0;
@@ -234,12 +251,128 @@ __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_me
     }
     if (L.wvalid && L.lw == 0) {
         LP[w] = lp;
-        SG[w] = sg;
+        SG[w] = sg + mk.done_mark;
         EL[w] = el;
         ACC[4 * w + 0] = s_e;
         ACC[4 * w + 1] = s_e2;
         ACC[4 * w + 2] = (double)n_acc;
         ACC[4 * w + 3] = (double)n_bad;
+    }
+}
+
+template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+__global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
+                                                 double *__restrict__ LP, double *__restrict__ SG,
+                                                 double *__restrict__ EL) {
+    extern __shared__ double smem[];
+    int64_t w;
+    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+    eval_wave<NMO, RT, MF, EXPL, BF>(S, L, w, X, LP, SG, EL, smem);
+}
+
+// skip_marked (mixed forms, every step of a call but its first): walkers
+// already marked belong to k_refine for the rest of the call and are left
+// alone, including their sign entry.
+template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+__global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_metropolis(DevSystem S, double *__restrict__ X,
+                                                      double *__restrict__ LP, double *__restrict__ SG,
+                                                      double *__restrict__ EL, int64_t W, int n_steps,
+                                                      double sigma, uint64_t seed, uint64_t step0,
+                                                      uint32_t walker_offset, double *__restrict__ ACC,
+                                                      int skip_marked) {
+    constexpr bool kMixed = sizeof(RT) != sizeof(double);
+    static_assert(!kMixed || metro_one_step<RT, MF, EXPL, BF>(), "a mixed step defers walkers one step at a time");
+    extern __shared__ double smem[];
+    int64_t w;
+    Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+    if (kMixed && skip_marked && L.wvalid && marked(SG[w])) {
+        L.wvalid = false;
+        L.active = false;
+    }
+    const int steps = metro_one_step<RT, MF, EXPL, BF>() ? 1 : n_steps;
+    const StepMarks mk{0.0, 0.0, kMixed ? mark_of(0, step0) : 0.0};
+    metropolis_wave<NMO, RT, MF, EXPL, BF>(S, L, w, X, LP, SG, EL, steps, sigma, seed, step0, walker_offset, ACC,
+                                            smem, mk);
+}
+
+// The refinement of a mixed evaluation (MC = false: every marked walker,
+// evaluated in FP64) or of Metropolis step `step` (MC = true: the walkers
+// marked for that step; last: the call's last step, which leaves them
+// unmarked, else they are marked lagging for the next step).  Work-group b
+// scans walkers [b span, (b + 1) span) 64 at a time and gathers the ones it
+// takes into its wave's walker slots, WPW at a time, so a few hundred
+// work-groups cover any W and each usually evaluates once or twice.  Every
+// work-group leaves the loop once its range is scanned.  Few waves run at
+// once, so the kernel takes the registers it wants (one wave per SIMD).
+constexpr int kRefineGroups = 1024;
+
+template <int NMO, typename RT, int MF, bool MC>
+__global__ __launch_bounds__(kWave, 3) void k_refine(DevSystem S, double *__restrict__ X, double *__restrict__ LP,
+                                                     double *__restrict__ SG, double *__restrict__ EL, int64_t W,
+                                                     int64_t span, double sigma, uint64_t seed, uint64_t step,
+                                                     int last, uint32_t walker_offset, double *__restrict__ ACC) {
+    extern __shared__ double smem[];
+    int64_t w0;
+    const Lane L0 = make_lane(S, 0, W, &w0);
+    const int64_t lo = (int64_t)blockIdx.x * span;
+    const int64_t hi = lo + span < W ? lo + span : W;
+    const int want = (int)(step & 3u);
+    int64_t next = lo;  // scan cursor, the same on every lane
+    while (next < hi) {
+        int64_t mine = -1;  // walker of this lane's slot
+        int found = 0;
+        while (found < S.WPW && next < hi) {
+            const int64_t q = next + L0.lane;
+            bool m = false;
+            if (q < hi) {
+                const double v = SG[q];
+                m = marked(v) && (!MC || (mark_code(v) & 3) == want);
+            }
+            uint64_t mask = __ballot(m ? 1 : 0);
+            int64_t adv = kWave;
+            while (mask != 0) {
+                const int b = __ffsll((unsigned long long)mask) - 1;
+                if (found == S.WPW) {
+                    adv = b;  // resume at the first walker not taken
+                    break;
+                }
+                if (L0.wloc == found) mine = next + b;
+                ++found;
+                mask &= mask - 1;
+            }
+            next += adv;
+        }
+        if (found == 0) break;
+        Lane L = L0;
+        L.wvalid = L0.wloc < found;
+        L.active = L.wvalid && L0.active;
+        const int64_t w = L.wvalid ? mine : 0;
+        if constexpr (!MC) {
+            eval_wave<NMO, double, 0, false, false>(S, L, w, X, LP, SG, EL, smem);
+        } else {
+            const double done = last ? 0.0 : mark_of(1, step + 1);
+            // lagging walkers first take the step in FP32 (a walker that
+            // needs FP64 becomes deferred), then the deferred ones in FP64
+            const double sv = L.wvalid ? SG[w] : 0.0;
+            Lane La = L;
+            La.wvalid = L.wvalid && (mark_code(sv) >> 2) == 1;
+            La.active = La.wvalid && L0.active;
+            if (__any(La.wvalid ? 1 : 0)) {
+                metropolis_wave<NMO, RT, MF, false, false>(S, La, w, X, LP, SG, EL, 1, sigma, seed, step,
+                                                           walker_offset, ACC, smem,
+                                                           StepMarks{mark_of(1, step), done, mark_of(0, step)});
+                __syncthreads();  // its stores before the loads below
+            }
+            const double sd = L.wvalid ? SG[w] : 0.0;
+            Lane Ld = L;
+            Ld.wvalid = L.wvalid && marked(sd) && mark_code(sd) == want;
+            Ld.active = Ld.wvalid && L0.active;
+            if (__any(Ld.wvalid ? 1 : 0))
+                metropolis_wave<NMO, double, 0, false, false>(S, Ld, w, X, LP, SG, EL, 1, sigma, seed, step,
+                                                              walker_offset, ACC, smem,
+                                                              StepMarks{mark_of(0, step), done, 0.0});
+        }
+        __syncthreads();  // the slots' stores before the next scan
     }
 }
 
@@ -297,38 +430,116 @@ __global__ __launch_bounds__(kWave, 1) void k_eval_fd(DevSystem S, const double 
 
 }  // namespace
 
-// One form at one compiled MO width: eval (mc = false) or a Metropolis block.
+// Refinement grid: ranges of whole 64-walker chunks over at most
+// kRefineGroups work-groups.
+struct RefineGrid {
+    int64_t span;
+    unsigned grid;
+    explicit RefineGrid(int64_t W) {
+        const int64_t chunks = (W + kWave - 1) / kWave;
+        const int64_t groups = chunks < 1 ? 1 : (chunks < kRefineGroups ? chunks : kRefineGroups);
+        span = ((chunks + groups - 1) / groups) * kWave;
+        grid = (unsigned)((W + span - 1) / span);
+    }
+};
+
+// Blocks of at least this many waves are split in two halves, one per
+// stream: a one-step launch ends with a partly filled last round of waves,
+// and the other stream's launch fills it.
+constexpr int64_t kSplitWaves = 1536;
+
+// One form at one compiled MO width: eval (mc = false) or a Metropolis
+// block.
+//  - Mixed eval: the eval launch, then k_refine on the same stream.
+//  - Mixed block: the step launches on st; after each, k_refine of that
+//    step on the side stream (it waits for the step's launch), and the step
+//    launch two steps later waits for it, so the side stream runs at most
+//    one step behind; st waits for the last one before the call returns.
+//  - Other one-step blocks: the walkers in two halves of whole waves, one
+//    per stream, when the block has kSplitWaves waves or more.
+//  - Otherwise one launch on st.
 template <int NMO, typename RT, int MF, bool EXPL = false, bool BF = false>
 static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL,
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
-                           uint32_t woff, double *ACC, hipStream_t st) {
+                           uint32_t woff, double *ACC, const CallStreams &cs) {
+    constexpr bool kMixed = sizeof(RT) != sizeof(double);
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
-    const int per = lds_per_walker<NMO, RT, EXPL, BF>(S);
-    size_t lds = (size_t)S.WPW * per * sizeof(double);
+    size_t lds = (size_t)S.WPW * lds_per_walker<NMO, RT, EXPL, BF>(S) * sizeof(double);
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
-    if (mc && metro_one_step<RT, MF, EXPL, BF>()) {
-        // one launch per step; the state and the running sums go through
-        // the caller's arrays between launches, so the result is the block's
-        for (int t = 0; t < n_steps; ++t) {
-            hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st,
-                               S, X, LP, SG, EL, W, 1, sigma, seed, step0 + (uint64_t)t, woff, ACC);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+    const hipStream_t st = cs.st;
+    hipError_t e = hipSuccess;
+    auto step_launch = [&](hipStream_t s, int64_t first, int64_t n, uint64_t step, int skip) {
+        const int64_t nb = (n + S.WPW - 1) / S.WPW;
+        hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)nb), dim3(kWave), lds, s, S,
+                           X + first * S.ne * 3, LP + first, SG + first, EL + first, n, 1, sigma, seed, step,
+                           woff + (uint32_t)first, ACC + 4 * first, skip);
+    };
+    if constexpr (kMixed) {
+        size_t rlds = (size_t)S.WPW * lds_per_walker<NMO, double, false, false>(S) * sizeof(double);
+        if (rlds < lds) rlds = lds;  // the refinement also runs the mixed step
+        const RefineGrid rg(W);
+        if (!mc) {
+            hipLaunchKernelGGL((k_eval<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
+                               (const double *)X, W, LP, SG, EL);
+            hipLaunchKernelGGL((k_refine<NMO, RT, MF, false>), dim3(rg.grid), dim3(kWave), rlds, st, S, X, LP, SG,
+                               EL, W, rg.span, 0.0, (uint64_t)0, (uint64_t)0, 0, (uint32_t)0, (double *)nullptr);
+            return hipGetLastError();
         }
-    } else if (mc)
-        hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st,
-                           S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
-    else
-        hipLaunchKernelGGL((k_eval<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
-                           (const double *)X, W, LP, SG, EL);
-    return hipGetLastError();
+        for (int t = 0; t < n_steps && e == hipSuccess; ++t) {
+            const uint64_t step = step0 + (uint64_t)t;
+            if (t >= 2) e = hipStreamWaitEvent(st, cs.ev[1 + (t - 2) % 3], 0);
+            if (e != hipSuccess) break;
+            step_launch(st, 0, W, step, t > 0 ? 1 : 0);
+            if ((e = hipGetLastError()) != hipSuccess) break;
+            if ((e = hipEventRecord(cs.ev[0], st)) != hipSuccess) break;
+            if ((e = hipStreamWaitEvent(cs.side, cs.ev[0], 0)) != hipSuccess) break;
+            hipLaunchKernelGGL((k_refine<NMO, RT, MF, true>), dim3(rg.grid), dim3(kWave), rlds, cs.side, S, X, LP,
+                               SG, EL, W, rg.span, sigma, seed, step, t == n_steps - 1 ? 1 : 0, woff, ACC);
+            if ((e = hipGetLastError()) != hipSuccess) break;
+            e = hipEventRecord(cs.ev[1 + t % 3], cs.side);
+        }
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, cs.ev[1 + (n_steps - 1) % 3], 0);
+        return e;
+    } else {
+        if (mc && metro_one_step<RT, MF, EXPL, BF>()) {
+            // one launch per step; the state and the running sums go
+            // through the caller's arrays between launches
+            const bool split = blocks >= kSplitWaves;
+            const int64_t wa = split ? ((blocks + 1) / 2) * S.WPW : W;
+            if (split) {
+                if ((e = hipEventRecord(cs.ev[0], st)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(cs.side, cs.ev[0], 0)) != hipSuccess) return e;
+            }
+            for (int t = 0; t < n_steps && e == hipSuccess; ++t) {
+                step_launch(st, 0, wa, step0 + (uint64_t)t, 0);
+                e = hipGetLastError();
+            }
+            if (split) {
+                for (int t = 0; t < n_steps && e == hipSuccess; ++t) {
+                    step_launch(cs.side, wa, W - wa, step0 + (uint64_t)t, 0);
+                    e = hipGetLastError();
+                }
+                if (e == hipSuccess) e = hipEventRecord(cs.ev[1], cs.side);
+                if (e == hipSuccess) e = hipStreamWaitEvent(st, cs.ev[1], 0);
+            }
+            return e;
+        }
+        if (mc) {
+            hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st,
+                               S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, 0);
+        } else {
+            hipLaunchKernelGGL((k_eval<NMO, RT, MF, EXPL, BF>), dim3((unsigned)blocks), dim3(kWave), lds, st, S,
+                               (const double *)X, W, LP, SG, EL);
+        }
+        return hipGetLastError();
+    }
 }
 
 // Signature shared by the per-form launchers.
 #define QMC_LAUNCH_ARGS                                                                            \
     bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL, int64_t W, int n_steps, \
-        double sigma, uint64_t seed, uint64_t step0, uint32_t woff, double *ACC, hipStream_t st
-#define QMC_LAUNCH_PASS mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st
+        double sigma, uint64_t seed, uint64_t step0, uint32_t woff, double *ACC, const CallStreams &cs
+#define QMC_LAUNCH_PASS mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, cs
 
 // Switch over the compiled MO widths.
 #define QMC_NMO_SWITCH(EXPR)                                                  \

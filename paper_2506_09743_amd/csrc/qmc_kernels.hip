@@ -7,15 +7,15 @@
 namespace qmc {
 
 hipError_t launch_form_fp64(bool, const DevSystem &, double *, double *, double *, double *, int64_t, int,
-                            double, uint64_t, uint64_t, uint32_t, double *, hipStream_t);
+                            double, uint64_t, uint64_t, uint32_t, double *, const CallStreams &);
 hipError_t launch_form_fp32(bool, const DevSystem &, double *, double *, double *, double *, int64_t, int,
-                            double, uint64_t, uint64_t, uint32_t, double *, hipStream_t);
+                            double, uint64_t, uint64_t, uint32_t, double *, const CallStreams &);
 hipError_t launch_form_bf16(bool, const DevSystem &, double *, double *, double *, double *, int64_t, int,
-                            double, uint64_t, uint64_t, uint32_t, double *, hipStream_t, int);
+                            double, uint64_t, uint64_t, uint32_t, double *, const CallStreams &, int);
 hipError_t launch_form_explicit(bool, const DevSystem &, double *, double *, double *, double *, int64_t, int,
-                                double, uint64_t, uint64_t, uint32_t, double *, hipStream_t);
+                                double, uint64_t, uint64_t, uint32_t, double *, const CallStreams &);
 hipError_t launch_form_backflow(bool, const DevSystem &, double *, double *, double *, double *, int64_t, int,
-                                double, uint64_t, uint64_t, uint32_t, double *, hipStream_t, bool);
+                                double, uint64_t, uint64_t, uint32_t, double *, const CallStreams &, bool);
 
 // Sums of the [W][4] accumulators over walkers in an order fixed by W:
 // thread t of the one work-group adds rows t, t + T, t + 2T, ... in turn,
@@ -76,7 +76,7 @@ size_t explicit_lds_bytes(const DevSystem &S) {
 // 6 FP64 with backflow and the low-rank configuration update.
 hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, double *LP, double *SG,
                           double *EL, int64_t W, int n_steps, double sigma, uint64_t seed,
-                          uint64_t step0, uint32_t woff, double *ACC, hipStream_t st) {
+                          uint64_t step0, uint32_t woff, double *ACC, const CallStreams &st) {
     switch (form) {
         case 0: return launch_form_fp64(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);
         case 1: return launch_form_fp32(mc, S, X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC, st);

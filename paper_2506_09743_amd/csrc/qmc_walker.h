@@ -767,17 +767,15 @@ __host__ __device__ inline int bf_pos_offset(const DevSystem &S);
 // PSI: stop once log|Psi| is known (no cofactor tables, no adjoint vector):
 // the values a finite-difference kinetic energy needs.  RT is the arithmetic
 // of the AO evaluation and MF the MO contraction of pass 1 (FP64 when RT is
-// double); hi (wave-uniform) switches a mixed form to the FP64 AO/MO path.
-// FULLT: the full table layout (walker_lds<NMO, true>), which the adjoint
-// reads; otherwise the compact one.
+// double).  FULLT: the full table layout (walker_lds<NMO, true>), which the
+// adjoint reads; otherwise the compact one.
 template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false, bool PSI = false,
           bool FULLT = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
-                                            double &x1, double &x2, Core<NMO> &c, void *stage = nullptr,
-                                            bool hi = false) {
-    // the compact layout serves the FP64 low-rank kernels (three waves per
-    // SIMD); the mixed forms run at two waves either way
-    constexpr bool kFull = FULLT || EXPL || BF || sizeof(RT) != sizeof(double);
+                                            double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
+    // the compact layout serves the low-rank Metropolis and evaluation
+    // kernels (fewer LDS bytes per wave, more waves per CU)
+    constexpr bool kFull = FULLT || EXPL || BF;
     const int nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
     const int c0 = tab_c0<NMO, kFull>(S), ts = tab_cols<NMO, kFull>(S);
     const int tstride = nmax * ts;                           // doubles per spin T table
@@ -826,7 +824,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
 
     // ---- pass 1: MO values of this electron ------------------------------
     double a[NMO];
-    if (sizeof(RT) == sizeof(double) || hi) {
+    if constexpr (sizeof(RT) == sizeof(double)) {
         double phi[NMO];
         mo_values<NMO, double>(S, x0, x1, x2, phi);
 #pragma unroll
