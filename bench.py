@@ -202,12 +202,12 @@ def grad_flops_per_walker(sysd) -> dict:
     return f
 
 
-def hbm_bytes_per_launch(sysd, W: int) -> int:
-    """Walker state read and written once per launch: X, log|Psi|, sign, E_L
-    and four accumulators, FP64."""
+def hbm_bytes_per_launch(sysd, W: int, steps: int) -> int:
+    """Walker state read and written once per step (the FP64 block takes one
+    kernel per step): X, log|Psi|, sign, E_L and four accumulators, FP64."""
     from paper_2506_09743_amd import synth
     per = (3 * synth.n_elec(sysd) + 7) * 8
-    return 2 * per * W
+    return 2 * per * W * steps
 
 
 def kernel_sha() -> str:
@@ -800,7 +800,7 @@ def main():
                            "per step and half of the walkers, the halves on two streams"),
                 "flops_per_walker_step": per_unit, "flops_per_walker_step_recount": fl["total"],
                 "walker_steps_per_launch": W * args.chunk,
-                "hbm_bytes_per_launch_algorithmic": hbm_bytes_per_launch(sysd, W),
+                "hbm_bytes_per_launch_algorithmic": hbm_bytes_per_launch(sysd, W, args.chunk),
                 "launch_ms_mean": main_form["launch_ms_mean"]}
     for form in results:
         if form == "fp64":

@@ -157,9 +157,12 @@ struct StepMarks {
 };
 
 // n_steps Metropolis steps of the valid walkers of a wave (w: this lane's
-// walker).  Mixed forms take one step per call and read a caller's sign
-// entry as its sign.
-template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+// walker).  Mixed forms read a caller's sign entry as its sign.  INL (mixed
+// forms): a walker whose proposal needs FP64 orbitals is evaluated again
+// with them right away (the wave runs the FP64 evaluation when any of its
+// walkers needs it), so any number of steps can be taken; otherwise mixed
+// forms take one step per call and defer such walkers.
+template <int NMO, typename RT, int MF, bool EXPL, bool BF, bool INL = false>
 __device__ __forceinline__ void metropolis_wave(const DevSystem &S, const Lane &L, int64_t w, double *__restrict__ X,
                                                 double *__restrict__ LP, double *__restrict__ SG,
                                                 double *__restrict__ EL, int n_steps, double sigma, uint64_t seed,
@@ -218,9 +221,18 @@ __device__ __forceinline__ void metropolis_wave(const DevSystem &S, const Lane &
         const double u = (double)bits * (1.0 / 9007199254740992.0);
 
         bool need;
-        const WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, y0, y1, y2, smem, need);
-        defer = kMixed && need;
-        if (defer) continue;  // one step per call in the mixed forms
+        WalkerResult r = eval_walker<NMO, RT, MF, EXPL, BF>(S, L, wsm, y0, y1, y2, smem, need);
+        if constexpr (kMixed && INL) {
+            if (__any(need ? 1 : 0)) {
+                bool unused;
+                const WalkerResult r64 =
+                    eval_walker<NMO, double, 0, false, false>(S, L, wsm, y0, y1, y2, smem, unused);
+                if (need) r = r64;
+            }
+        } else {
+            defer = kMixed && need;
+            if (defer) continue;  // one step per call
+        }
         const bool acc = isfinite(r.logpsi) && (u < exp(2.0 * (r.logpsi - lp)));
         if (acc) {
             x0 = y0;
@@ -293,6 +305,27 @@ __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_me
     const StepMarks mk{0.0, 0.0, kMixed ? mark_of(0, step0) : 0.0};
     metropolis_wave<NMO, RT, MF, EXPL, BF>(S, L, w, X, LP, SG, EL, steps, sigma, seed, step0, walker_offset, ACC,
                                             smem, mk);
+}
+
+// Metropolis block in one launch (step loop) for blocks of at most
+// kLoopWaves waves, the low-rank forms without backflow: with one wave per
+// SIMD every wave is resident at once, so a step costs one wave's latency
+// whether it is one launch or one loop trip, and the loop saves a launch
+// per step (small molecules and small requests would otherwise be bound by
+// launches).  Mixed forms refine inside the loop.
+constexpr int64_t kLoopWaves = 1024;
+
+template <int NMO, typename RT, int MF>
+__global__ __launch_bounds__(kWave, 1) void k_metropolis_loop(DevSystem S, double *__restrict__ X,
+                                                              double *__restrict__ LP, double *__restrict__ SG,
+                                                              double *__restrict__ EL, int64_t W, int n_steps,
+                                                              double sigma, uint64_t seed, uint64_t step0,
+                                                              uint32_t walker_offset, double *__restrict__ ACC) {
+    extern __shared__ double smem[];
+    int64_t w;
+    const Lane L = make_lane(S, (int64_t)blockIdx.x * S.WPW, W, &w);
+    metropolis_wave<NMO, RT, MF, false, false, true>(S, L, w, X, LP, SG, EL, n_steps, sigma, seed, step0,
+                                                     walker_offset, ACC, smem, StepMarks{0.0, 0.0, 0.0});
 }
 
 // The refinement of a mixed evaluation (MC = false: every marked walker,
@@ -457,6 +490,8 @@ constexpr int64_t kSplitWaves = 1536;
 //    one step behind; st waits for the last one before the call returns.
 //  - Other one-step blocks: the walkers in two halves of whole waves, one
 //    per stream, when the block has kSplitWaves waves or more.
+//  - Blocks of at most kLoopWaves waves (low-rank, no backflow, any
+//    form): one k_metropolis_loop launch on st.
 //  - Otherwise one launch on st.
 template <int NMO, typename RT, int MF, bool EXPL = false, bool BF = false>
 static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL,
@@ -468,6 +503,15 @@ static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, d
     if (MF > 0 && lds < (size_t)kStageBytes) lds = kStageBytes;
     const hipStream_t st = cs.st;
     hipError_t e = hipSuccess;
+    if constexpr (!EXPL && !BF) {
+        if (mc && blocks <= kLoopWaves) {
+            size_t llds = (size_t)S.WPW * lds_per_walker<NMO, double, false, false>(S) * sizeof(double);
+            if (llds < lds) llds = lds;
+            hipLaunchKernelGGL((k_metropolis_loop<NMO, RT, MF>), dim3((unsigned)blocks), dim3(kWave), llds, st, S,
+                               X, LP, SG, EL, W, n_steps, sigma, seed, step0, woff, ACC);
+            return hipGetLastError();
+        }
+    }
     auto step_launch = [&](hipStream_t s, int64_t first, int64_t n, uint64_t step, int skip) {
         const int64_t nb = (n + S.WPW - 1) / S.WPW;
         hipLaunchKernelGGL((k_metropolis<NMO, RT, MF, EXPL, BF>), dim3((unsigned)nb), dim3(kWave), lds, s, S,

@@ -68,3 +68,23 @@ def test_mixed_block_signs_and_single_steps(torch_cuda, qmc, prec):
           f"acceptance {acc_a[:, 2].sum():.0f} vs {acc_b[:, 2].sum():.0f}")
     assert all(same)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_small_block_loop_equals_large_block(torch_cuda, qmc, prec):
+    """Blocks of at most 1024 waves run as one looping launch (mixed forms
+    refine inside it); larger ones one launch per step.  The first 4096 CO
+    walkers (1024 waves) advanced alone equal the same walkers inside a
+    65536-walker block, bit for bit."""
+    torch = torch_cuda
+    W, B = 65536, 4096
+    s, X0 = _co(torch, qmc, W, 23)
+    lp0, sg0, el0 = s.eval(X0, precision=prec)
+    A = [X0.clone(), lp0.clone(), sg0.clone(), el0.clone()]
+    accA = s.metropolis(*A, 5, 0.2, 777, step0=3, precision=prec)
+    P = [t[:B].clone() for t in (X0, lp0, sg0, el0)]
+    accP = s.metropolis(*P, 5, 0.2, 777, step0=3, precision=prec)
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(A + [accA], P + [accP])):
+        assert torch.equal(a[:B], b), k
+    s.close()
