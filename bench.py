@@ -375,9 +375,10 @@ def many_body_bench(sysd, args, dev, seed) -> dict:
 
 
 def grad_bench(args, dev) -> dict:
-    """The hand-written adjoint on the Li2 workload (32768 walkers, FP64,
-    all four outputs): walker-gradients/s, ms per call, roofline against
-    the FP64 vector peak on the algorithmic estimate."""
+    """The hand-written adjoint on the Li2 workload (32768 walkers, all four
+    outputs), FP64 and the mixed FP32 form: walker-gradients/s, ms per call,
+    roofline of the FP64 call against the FP64 vector peak on the term-by-term
+    algorithmic count."""
     import torch
     from paper_2506_09743_amd import qmc, synth
     sysd = synth.make_system("Li2")
@@ -389,16 +390,19 @@ def grad_bench(args, dev) -> dict:
             torch.empty((W, P), dtype=torch.float64, device=dev),
             torch.empty((W, A, 3), dtype=torch.float64, device=dev),
             torch.empty((W, A, 3), dtype=torch.float64, device=dev)]
-    qmc.qmc_grad(system.handle, X, *outs)
-    ts = []
-    for _ in range(5):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        qmc.qmc_grad(system.handle, X, *outs)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    ms = float(np.median(ts))
+    def timed(prec):
+        qmc.qmc_grad(system.handle, X, *outs, precision=prec)
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            qmc.qmc_grad(system.handle, X, *outs, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    ms_fp32 = timed(qmc.QMC_MIXED_FP32)
+    ms = timed(qmc.QMC_FP64)
     fl = grad_flops_per_walker(sysd)
     achieved = fl["total"] * W / (ms * 1e-3)
     out_bytes = W * (2 * P + 2 * 3 * A) * 8 + W * synth.n_elec(sysd) * 3 * 8
@@ -406,6 +410,7 @@ def grad_bench(args, dev) -> dict:
     return {"workload": f"Li2, {W} walkers, d log|Psi|/d theta, d E_L/d theta ({P} parameters), "
                         "d log|Psi|/d R, d E_L/d R",
             "ms_per_call": ms, "walker_gradients_per_s": W / (ms * 1e-3), "dtype": "f64",
+            "mixed_fp32": {"ms_per_call": ms_fp32, "walker_gradients_per_s": W / (ms_fp32 * 1e-3)},
             "flops_per_walker": fl["total"], "flops_per_walker_terms": fl, "hbm_bytes_per_call": out_bytes,
             "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,

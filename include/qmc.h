@@ -229,10 +229,14 @@ qmc_status qmc_eval_eloc_fd(qmc_system *sys, const double *d_X, int64_t W, doubl
      d_dlogpsi_dR   [W][n_atoms][3]  d log|Psi| / d R_alpha
      d_deloc_dR     [W][n_atoms][3]  d E_L / d R_alpha (includes V_nn)
    Any output may be NULL; at least one must not be.  d_X as in
-   qmc_eval_psi_eloc.  Returns QMC_EUNSUPPORTED when the walker tables do not
-   fit the 160 KiB of LDS of a compute unit and for systems with
-   backflow. */
-qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
+   qmc_eval_psi_eloc.  precision: QMC_FP64, or QMC_MIXED_FP32 (the AO values
+   and the MO value contraction of the forward evaluation in FP32, as in
+   qmc_eval_psi_eloc's mixed form without its FP64 re-evaluation; every
+   derivative pass FP64); the other forms return QMC_EUNSUPPORTED, a value
+   outside qmc_precision QMC_EINVAL.  Returns QMC_EUNSUPPORTED when the
+   walker tables do not fit the 160 KiB of LDS of a compute unit and for
+   systems with backflow. */
+qmc_status qmc_grad(qmc_system *sys, int32_t precision, const double *d_X, int64_t W, double *d_dlogpsi,
                     double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream);
 
 /* Number of variational parameters in the qmc_grad layout. */

@@ -22,7 +22,7 @@ hipError_t launch_walkers(bool mc, int form, const DevSystem &S, double *X, doub
                           uint64_t step0, uint32_t woff, double *ACC, const CallStreams &cs);
 int padded_mo(int n_mo);
 hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *dlogpsi,
-                       double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param,
+                       double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param, bool mixed,
                        hipStream_t st);
 size_t grad_lds_bytes(const DevSystem &S);
 size_t explicit_lds_bytes(const DevSystem &S);
@@ -708,9 +708,11 @@ qmc_status qmc_eval_eloc_fd(qmc_system *sys, const double *d_X, int64_t W, doubl
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 
-qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlogpsi,
+qmc_status qmc_grad(qmc_system *sys, int32_t precision, const double *d_X, int64_t W, double *d_dlogpsi,
                     double *d_deloc_dtheta, double *d_dlogpsi_dR, double *d_deloc_dR, void *stream) {
     if (!sys || W < 0 || W > (int64_t)0x7FFFFFFF) return QMC_EINVAL;
+    if (precision < QMC_FP64 || precision > QMC_FP64_EXPLICIT) return QMC_EINVAL;
+    if (precision != QMC_FP64 && precision != QMC_MIXED_FP32) return QMC_EUNSUPPORTED;
     if (W == 0) return QMC_OK;
     if (!d_X || (!d_dlogpsi && !d_deloc_dtheta && !d_dlogpsi_dR && !d_deloc_dR)) return QMC_EINVAL;
     if (qmc::grad_lds_bytes(sys->S) > 160 * 1024) return QMC_EUNSUPPORTED;
@@ -718,7 +720,7 @@ qmc_status qmc_grad(qmc_system *sys, const double *d_X, int64_t W, double *d_dlo
     DeviceGuard g(sys->device);
     if (!g.ok) return QMC_EDEVICE;
     hipError_t e = qmc::launch_grad(sys->S, d_X, W, d_dlogpsi, d_deloc_dtheta, d_dlogpsi_dR, d_deloc_dR,
-                                    (int)sys->n_params, (hipStream_t)stream);
+                                    (int)sys->n_params, precision == QMC_MIXED_FP32, (hipStream_t)stream);
     return e == hipSuccess ? QMC_OK : QMC_EDEVICE;
 }
 

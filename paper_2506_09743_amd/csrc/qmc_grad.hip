@@ -157,7 +157,10 @@ __device__ __forceinline__ Radial radial_full(const DevSystem &S, int p0, int np
     return R;
 }
 
-template <int NMO>
+// RT: arithmetic of the forward evaluation's AO values and MO value
+// contraction (double, or float for the mixed FP32 form); everything the
+// adjoint adds is FP64.
+template <int NMO, typename RT>
 __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__restrict__ X, int64_t W,
                                                 GradOut G) {
     extern __shared__ double smem[];
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
 
     // ---- shared stages: MO values, Gauss-Jordan, determinants, a_e ----------
     Core<NMO> c;
-    core_stages<NMO, double, 0, false, false, false, true>(S, L, wsm, x0, x1, x2, c);
+    core_stages<NMO, RT, 0, false, false, false, true>(S, L, wsm, x0, x1, x2, c);
     const double gJ[3] = {c.gJ0, c.gJ1, c.gJ2};
     const double *Tg = sT + L.grp * ts;
     const double *Cg = sC + L.grp * ts;
@@ -560,12 +563,15 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
 }  // namespace
 
 template <int NMO>
-static hipError_t launch_grad_t(const DevSystem &S, const double *X, int64_t W, const GradOut &G,
+static hipError_t launch_grad_t(const DevSystem &S, const double *X, int64_t W, const GradOut &G, bool mixed,
                                 hipStream_t st) {
     const int64_t blocks = (W + S.WPW - 1) / S.WPW;
     const size_t lds =
         (size_t)S.WPW * (walker_lds<NMO>(S) + grad_extra_lds<NMO>(S)) * sizeof(double);
-    hipLaunchKernelGGL((k_grad<NMO>), dim3((unsigned)blocks), dim3(kWave), lds, st, S, X, W, G);
+    if (mixed)
+        hipLaunchKernelGGL((k_grad<NMO, float>), dim3((unsigned)blocks), dim3(kWave), lds, st, S, X, W, G);
+    else
+        hipLaunchKernelGGL((k_grad<NMO, double>), dim3((unsigned)blocks), dim3(kWave), lds, st, S, X, W, G);
     return hipGetLastError();
 }
 
@@ -581,17 +587,17 @@ size_t grad_lds_bytes(const DevSystem &S) {
 }
 
 hipError_t launch_grad(const DevSystem &S, const double *X, int64_t W, double *dlogpsi,
-                       double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param,
+                       double *deloc_dth, double *dlogpsi_dR, double *deloc_dR, int n_param, bool mixed,
                        hipStream_t st) {
     GradOut G{dlogpsi, deloc_dth, dlogpsi_dR, deloc_dR, n_param};
     switch (S.nmo_pad) {
-        case 4: return launch_grad_t<4>(S, X, W, G, st);
-        case 8: return launch_grad_t<8>(S, X, W, G, st);
-        case 12: return launch_grad_t<12>(S, X, W, G, st);
-        case 16: return launch_grad_t<16>(S, X, W, G, st);
-        case 20: return launch_grad_t<20>(S, X, W, G, st);
-        case 24: return launch_grad_t<24>(S, X, W, G, st);
-        case 32: return launch_grad_t<32>(S, X, W, G, st);
+        case 4: return launch_grad_t<4>(S, X, W, G, mixed, st);
+        case 8: return launch_grad_t<8>(S, X, W, G, mixed, st);
+        case 12: return launch_grad_t<12>(S, X, W, G, mixed, st);
+        case 16: return launch_grad_t<16>(S, X, W, G, mixed, st);
+        case 20: return launch_grad_t<20>(S, X, W, G, mixed, st);
+        case 24: return launch_grad_t<24>(S, X, W, G, mixed, st);
+        case 32: return launch_grad_t<32>(S, X, W, G, mixed, st);
     }
     return hipErrorInvalidValue;
 }

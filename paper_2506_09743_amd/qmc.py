@@ -74,8 +74,8 @@ def lib():
                                            C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64,
                                            C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p]
         L.qmc_metropolis_block.restype = C.c_int
-        L.qmc_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p]
+        L.qmc_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p]
         L.qmc_grad.restype = C.c_int
         L.qmc_eval_eloc_fd.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
                                        C.c_void_p, C.c_void_p]
@@ -198,13 +198,14 @@ def qmc_eval_eloc_fd(handle, X, h: float, logpsi, eloc) -> None:
                                   _dev_ptr(eloc, "eloc", (W,)), _stream()), "qmc_eval_eloc_fd")
 
 
-def qmc_grad(handle, X, dlogpsi=None, deloc_dtheta=None, dlogpsi_dR=None, deloc_dR=None) -> None:
+def qmc_grad(handle, X, dlogpsi=None, deloc_dtheta=None, dlogpsi_dR=None, deloc_dR=None,
+             precision: int = QMC_FP64) -> None:
     W = X.shape[0]
 
     def opt(t, name):
         return _dev_ptr(t, name) if t is not None else None
 
-    _check(lib().qmc_grad(handle, _dev_ptr(X, "X"), W, opt(dlogpsi, "dlogpsi"),
+    _check(lib().qmc_grad(handle, precision, _dev_ptr(X, "X"), W, opt(dlogpsi, "dlogpsi"),
                           opt(deloc_dtheta, "deloc_dtheta"), opt(dlogpsi_dR, "dlogpsi_dR"),
                           opt(deloc_dR, "deloc_dR"), _stream()), "qmc_grad")
 
@@ -276,16 +277,17 @@ class System:
         qmc_eval_eloc_fd(self.handle, X, h, *out)
         return tuple(out)
 
-    def grad(self, X):
+    def grad(self, X, precision="fp64"):
         """(d log|Psi|/d theta [W,P], d E_L/d theta [W,P], d log|Psi|/d R [W,A,3],
-        d E_L/d R [W,A,3]) in FP64."""
+        d E_L/d R [W,A,3]), FP64 outputs; precision "fp64" or "fp32" (the
+        forward evaluation's AO values and MO value contraction in FP32)."""
         import torch
         W, P, A = self._walkers(X), self.param_count, self.n_atoms
         out = [torch.empty((W, P), dtype=torch.float64, device=X.device),
                torch.empty((W, P), dtype=torch.float64, device=X.device),
                torch.empty((W, A, 3), dtype=torch.float64, device=X.device),
                torch.empty((W, A, 3), dtype=torch.float64, device=X.device)]
-        qmc_grad(self.handle, X, *out)
+        qmc_grad(self.handle, X, *out, precision=PRECISIONS[precision])
         return tuple(out)
 
     def metropolis(self, X, logpsi, sign, eloc, n_steps, sigma, seed, step0=0, walker_offset=0,

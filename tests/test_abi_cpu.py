@@ -101,7 +101,7 @@ def test_null_arguments_rejected():
     assert L.qmc_system_create(None, 0, C.byref(C.c_void_p())) == qmc.QMC_EINVAL
     assert L.qmc_eval_psi_eloc(None, 0, None, 1, None, None, None, None) == qmc.QMC_EINVAL
     assert L.qmc_metropolis_block(None, 0, None, None, None, None, 1, 1, 0.2, 0, 0, 0, None, None) == qmc.QMC_EINVAL
-    assert L.qmc_grad(None, None, 1, None, None, None, None, None) == qmc.QMC_EINVAL
+    assert L.qmc_grad(None, 0, None, 1, None, None, None, None, None) == qmc.QMC_EINVAL
     assert L.qmc_eval_eloc_fd(None, None, 1, 1e-3, None, None, None) == qmc.QMC_EINVAL
     assert L.qmc_param_count(None) == -1
     assert L.qmc_bytes_per_walker(None, 0) == 0

@@ -143,3 +143,53 @@ def test_force_estimator_on_gpu_outputs(oracle_mod):
     assert torch.isfinite(F).all() and torch.isfinite(g).all()
     assert F.shape == (2, 3) and g.shape == (s.param_count,)
     s.close()
+
+
+@pytest.mark.parametrize("name,nw,mbj", [("Li2", 4, False), ("Li2", 3, True)])
+def test_grad_mixed_fp32_vs_oracle_fd(oracle_mod, name, nw, mbj):
+    """The mixed FP32 form of qmc_grad (forward AO values and MO value
+    contraction in FP32, every derivative pass FP64) on Li2 against the same
+    FP64 oracle central differences, h = 1e-5: within 1e-4 of the scale
+    (FP32 orbital rounding, about 1e-7 relative, amplified by the Slater
+    inverse and the kinetic terms; measured 1.3e-5 and 1.6e-5), and within
+    1e-4 of the FP64 form's own outputs."""
+    import torch
+    from paper_2506_09743_amd import qmc
+    sysd = synth.make_system(name)
+    if mbj:
+        sysd = synth.with_many_body_jastrow(sysd, synth.MBJ_SEED[name], symmetric=False)
+        sysd["jas_een"][:, 0] *= 10.0
+    o = oracle_mod.OracleSystem(sysd)
+    X = _good_walkers(o, sysd, nw, 12)
+    s = qmc.System(sysd)
+    tX = torch.from_numpy(X).cuda()
+    dl, de, dlR, deR = [t.cpu().numpy() for t in s.grad(tX, precision="fp32")]
+    g64 = [t.cpu().numpy() for t in s.grad(tX)]
+    n_prim = sysd["prim_exp"].size
+    nao, nmo = sysd["mo_coef"].shape
+    p_b = n_prim + nao * nmo
+    cols = list(range(n_prim)) + list(range(p_b, s.param_count))
+    cols += list(n_prim + np.random.default_rng(1).choice(nao * nmo, 24, replace=False))
+    n_en = sysd["jas_en"].size if mbj else 0
+    worst = 0.0
+    for c in cols:
+        c = int(c)
+        if c < n_prim:
+            kind, idx = "exp", c
+        elif c == p_b:
+            kind, idx = "b", None
+        elif c > p_b + n_en:
+            kind, idx = "jas_een", np.unravel_index(c - p_b - 1 - n_en, sysd["jas_een"].shape)
+        elif c > p_b:
+            kind, idx = "jas_en", np.unravel_index(c - p_b - 1, sysd["jas_en"].shape)
+        else:
+            kind, idx = "mo", ((c - n_prim) // nmo, (c - n_prim) % nmo)
+        fl, fe = _fd(oracle_mod, sysd, X, kind, idx)
+        for ana, fd in ((dl[:, c], fl), (de[:, c], fe)):
+            worst = max(worst, float(np.max(np.abs(ana - fd) / np.maximum(1.0, np.abs(fd)))))
+    for a, b in zip((dl, de, dlR, deR), g64):
+        scale = np.maximum(1.0, np.abs(b))
+        worst = max(worst, float(np.max(np.abs(a - b) / scale)))
+    print(f"{name}{' many-body' if mbj else ''} FP32 grad: max scaled error {worst:.2e}")
+    assert worst < 1e-4
+    s.close()
