@@ -481,13 +481,21 @@ struct RefineGrid {
 // and the other stream's launch fills it.
 constexpr int64_t kSplitWaves = 1536;
 
+// Mixed blocks of more than this many waves refine on the second stream,
+// one step behind (five runtime calls per step); smaller ones refine after
+// each step on the caller's stream (two calls per step), where the
+// refinement's latency is left to other work on the device to fill.
+constexpr int64_t kLagWaves = 8192;
+
 // One form at one compiled MO width: eval (mc = false) or a Metropolis
 // block.
 //  - Mixed eval: the eval launch, then k_refine on the same stream.
-//  - Mixed block: the step launches on st; after each, k_refine of that
-//    step on the side stream (it waits for the step's launch), and the step
-//    launch two steps later waits for it, so the side stream runs at most
-//    one step behind; st waits for the last one before the call returns.
+//  - Mixed block of more than kLagWaves waves: the step launches on st;
+//    after each, k_refine of that step on the side stream (it waits for the
+//    step's launch), and the step launch two steps later waits for it, so
+//    the side stream runs at most one step behind; st waits for the last
+//    one before the call returns.  Smaller mixed blocks: each step launch
+//    followed by its k_refine on st.
 //  - Other one-step blocks: the walkers in two halves of whole waves, one
 //    per stream, when the block has kSplitWaves waves or more.
 //  - Blocks of at most kLoopWaves waves (low-rank, no backflow, any
@@ -528,6 +536,16 @@ static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, d
             hipLaunchKernelGGL((k_refine<NMO, RT, MF, false>), dim3(rg.grid), dim3(kWave), rlds, st, S, X, LP, SG,
                                EL, W, rg.span, 0.0, (uint64_t)0, (uint64_t)0, 0, (uint32_t)0, (double *)nullptr);
             return hipGetLastError();
+        }
+        if (blocks <= kLagWaves) {
+            for (int t = 0; t < n_steps && e == hipSuccess; ++t) {
+                const uint64_t step = step0 + (uint64_t)t;
+                step_launch(st, 0, W, step, 0);
+                hipLaunchKernelGGL((k_refine<NMO, RT, MF, true>), dim3(rg.grid), dim3(kWave), rlds, st, S, X, LP,
+                                   SG, EL, W, rg.span, sigma, seed, step, 1, woff, ACC);
+                e = hipGetLastError();
+            }
+            return e;
         }
         for (int t = 0; t < n_steps && e == hipSuccess; ++t) {
             const uint64_t step = step0 + (uint64_t)t;

@@ -70,14 +70,17 @@ def test_mixed_block_signs_and_single_steps(torch_cuda, qmc, prec):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_small_block_loop_equals_large_block(torch_cuda, qmc, prec):
+@pytest.mark.parametrize("prec,B", [("fp64", 4096), ("fp32", 4096), ("bf16", 4096), ("fp32", 16384),
+                                    ("bf16", 16384), ("fp64", 6000)])
+def test_small_block_loop_equals_large_block(torch_cuda, qmc, prec, B):
     """Blocks of at most 1024 waves run as one looping launch (mixed forms
-    refine inside it); larger ones one launch per step.  The first 4096 CO
-    walkers (1024 waves) advanced alone equal the same walkers inside a
-    65536-walker block, bit for bit."""
+    refine inside it); larger ones one launch per step, mixed blocks of up
+    to 8192 waves refining on the caller's stream after each step, larger
+    ones on the second stream.  The first B CO walkers (4096: 1024 waves;
+    16384: 4096 waves; 6000: 1500 waves, one stream) advanced alone equal
+    the same walkers inside a 65536-walker block, bit for bit."""
     torch = torch_cuda
-    W, B = 65536, 4096
+    W = 65536
     s, X0 = _co(torch, qmc, W, 23)
     lp0, sg0, el0 = s.eval(X0, precision=prec)
     A = [X0.clone(), lp0.clone(), sg0.clone(), el0.clone()]
