@@ -14,8 +14,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmc.so")
-SOURCES = ["qmc_api.hip", "qmc_kernels.hip", "qmc_form_fp64.hip", "qmc_form_fp32.hip",
-           "qmc_form_bf16.hip", "qmc_form_backflow.hip", "qmc_grad.hip"]
+# longest compiles first
+SOURCES = ["qmc_form_bf16.hip", "qmc_form_bf16_x1.hip", "qmc_form_fp32.hip", "qmc_form_backflow.hip",
+           "qmc_form_backflow_max.hip", "qmc_form_fp64.hip", "qmc_grad.hip", "qmc_api.hip", "qmc_kernels.hip"]
 ARCH = os.environ.get("QMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

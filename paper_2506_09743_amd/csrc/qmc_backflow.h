@@ -265,7 +265,7 @@ __device__ __forceinline__ void mo_channels_bf(const DevSystem &S, double q0, do
 // LR: configurations from the reference by the rank <= 2 update of
 // eq. table (only A0 is factorised); otherwise every configuration is
 // factorised on its own.
-template <int NMO, bool LR>
+template <int NMO, bool LR, int CAP>
 __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L, double *wsm, const double *sPos,
                                               double x0, double x1, double x2, Core<NMO> &c) {
     const int LW = S.LW, nmax = S.n_up > S.n_dn ? S.n_up : S.n_dn;
@@ -514,7 +514,8 @@ __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L,
     }
 
     // ---- every configuration of each spin --------------------------------
-    double gtab[kMaxCfgBF * 3], vtab[kMaxCfgBF * 3];
+    // per-configuration rows of this lane (CAP >= the system's configurations per spin)
+    double gtab[CAP * 3], vtab[CAP * 3];
     for (int q = 0; q < ncmax; ++q) {
         const bool live = q < ncfg_g;
         double t1 = 0.0, clog = -INFINITY, csgn = 0.0;

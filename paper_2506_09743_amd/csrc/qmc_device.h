@@ -87,5 +87,9 @@ struct DevSystem {
 constexpr int kMaxEen = 8;
 // Largest number of distinct spin configurations per spin with backflow.
 constexpr int kMaxCfgBF = 128;
+// Backflow kernels are compiled for two table sizes: up to kSmallCfgBF
+// configurations per spin (smaller private tables per lane) and up to
+// kMaxCfgBF.
+constexpr int kSmallCfgBF = 48;
 
 }  // namespace qmc

@@ -1,4 +1,5 @@
-// Instantiates the inverse-backflow forms: the low-rank configuration update
+// Instantiates the inverse-backflow forms for expansions of up to
+// kSmallCfgBF configurations per spin: the low-rank configuration update
 // (QMC_FP64 with backflow) and every configuration factorised
 // (QMC_FP64_EXPLICIT with backflow).
 
@@ -6,11 +7,16 @@
 
 namespace qmc {
 
+hipError_t launch_form_backflow_max(QMC_LAUNCH_ARGS, bool low_rank);
+
 hipError_t launch_form_backflow(QMC_LAUNCH_ARGS, bool low_rank) {
+    // BF = 1: per-lane tables for up to kSmallCfgBF configurations per spin;
+    // larger expansions take the kMaxCfgBF kernels (qmc_form_backflow_max.hip)
+    if (S.n_cfg_max > kSmallCfgBF) return launch_form_backflow_max(QMC_LAUNCH_PASS, low_rank);
     if (low_rank) {
-        QMC_NMO_SWITCH(return (launch_t<N, double, 0, false, true>(QMC_LAUNCH_PASS)))
+        QMC_NMO_SWITCH(return (launch_t<N, double, 0, false, 1>(QMC_LAUNCH_PASS)))
     }
-    QMC_NMO_SWITCH(return (launch_t<N, double, 0, true, true>(QMC_LAUNCH_PASS)))
+    QMC_NMO_SWITCH(return (launch_t<N, double, 0, true, 1>(QMC_LAUNCH_PASS)))
 }
 
 size_t backflow_lds_bytes(const DevSystem &S, bool low_rank) {

@@ -28,7 +28,7 @@ constexpr double kRefineKinetic = 3.0e4;
 // lane of the block must call it (it contains block barriers); results are
 // identical on all lanes of a walker.  need: a mixed form's result must be
 // refined in FP64 (kinetic energy not finite or above kRefineKinetic).
-template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+template <int NMO, typename RT, int MF, bool EXPL, int BF>
 __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const Lane &L, double *wsm, double x0,
                                                     double x1, double x2, void *stage, bool &need) {
     Core<NMO> c;
@@ -72,7 +72,7 @@ __device__ __forceinline__ WalkerResult eval_walker(const DevSystem &S, const La
     return res;
 }
 
-template <int NMO, typename RT, bool EXPL, bool BF>
+template <int NMO, typename RT, bool EXPL, int BF>
 __host__ __device__ inline int lds_per_walker(const DevSystem &S) {
     if constexpr (BF) return walker_lds_bf<NMO, !EXPL>(S);
     else if constexpr (EXPL) return walker_lds_explicit<NMO>(S);
@@ -89,10 +89,10 @@ __host__ __device__ inline int lds_per_walker(const DevSystem &S) {
 // wave and run at two.  The explicit kernel runs the block in one launch at
 // one wave (its LDS and registers), the backflow kernels one step per launch
 // at one wave.
-template <typename RT, int MF, bool EXPL, bool BF>
+template <typename RT, int MF, bool EXPL, int BF>
 constexpr bool metro_one_step() { return BF || !EXPL; }
 
-template <typename RT, int MF, bool EXPL, bool BF>
+template <typename RT, int MF, bool EXPL, int BF>
 constexpr int metro_waves() { return (EXPL || BF) ? 1 : (MF == 0 ? 3 : 2); }
 
 // Refinement of the mixed forms.  A walker whose FP32 result needs FP64
@@ -122,7 +122,7 @@ __device__ __forceinline__ int mark_code(double sg) { return (int)rint(sg / kMar
 // One evaluation of the walkers of a wave (w: this lane's walker).  A mixed
 // form defers the walkers to refine (their log|Psi| and E_L are left
 // unwritten); the refinement evaluates them again in FP64.
-template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+template <int NMO, typename RT, int MF, bool EXPL, int BF>
 __device__ __forceinline__ void eval_wave(const DevSystem &S, const Lane &L, int64_t w, const double *__restrict__ X,
                                           double *__restrict__ LP, double *__restrict__ SG,
                                           double *__restrict__ EL, double *smem) {
@@ -162,7 +162,7 @@ struct StepMarks {
 // with them right away (the wave runs the FP64 evaluation when any of its
 // walkers needs it), so any number of steps can be taken; otherwise mixed
 // forms take one step per call and defer such walkers.
-template <int NMO, typename RT, int MF, bool EXPL, bool BF, bool INL = false>
+template <int NMO, typename RT, int MF, bool EXPL, int BF, bool INL = false>
 __device__ __forceinline__ void metropolis_wave(const DevSystem &S, const Lane &L, int64_t w, double *__restrict__ X,
                                                 double *__restrict__ LP, double *__restrict__ SG,
                                                 double *__restrict__ EL, int n_steps, double sigma, uint64_t seed,
@@ -272,7 +272,7 @@ __device__ __forceinline__ void metropolis_wave(const DevSystem &S, const Lane &
     }
 }
 
-template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+template <int NMO, typename RT, int MF, bool EXPL, int BF>
 __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, const double *__restrict__ X, int64_t W,
                                                  double *__restrict__ LP, double *__restrict__ SG,
                                                  double *__restrict__ EL) {
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kWave, (MF > 0 ? 2 : 1)) void k_eval(DevSystem S, c
 // skip_marked (mixed forms, every step of a call but its first): walkers
 // already marked belong to k_refine for the rest of the call and are left
 // alone, including their sign entry.
-template <int NMO, typename RT, int MF, bool EXPL, bool BF>
+template <int NMO, typename RT, int MF, bool EXPL, int BF>
 __global__ __launch_bounds__(kWave, (metro_waves<RT, MF, EXPL, BF>())) void k_metropolis(DevSystem S, double *__restrict__ X,
                                                       double *__restrict__ LP, double *__restrict__ SG,
                                                       double *__restrict__ EL, int64_t W, int n_steps,
@@ -501,7 +501,7 @@ constexpr int64_t kLagWaves = 8192;
 //  - Blocks of at most kLoopWaves waves (low-rank, no backflow, any
 //    form): one k_metropolis_loop launch on st.
 //  - Otherwise one launch on st.
-template <int NMO, typename RT, int MF, bool EXPL = false, bool BF = false>
+template <int NMO, typename RT, int MF, bool EXPL = false, int BF = 0>
 static hipError_t launch_t(bool mc, const DevSystem &S, double *X, double *LP, double *SG, double *EL,
                            int64_t W, int n_steps, double sigma, uint64_t seed, uint64_t step0,
                            uint32_t woff, double *ACC, const CallStreams &cs) {

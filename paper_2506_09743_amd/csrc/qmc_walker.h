@@ -757,7 +757,7 @@ __device__ __forceinline__ void explicit_dets(const DevSystem &S, const Lane &L,
 // Backflow: grad and Laplacian of Sigma of the backflow-transformed
 // determinants (eq. nabla_d), every configuration explicitly.  Every lane of
 // the block must call it.  sPos holds the walker's bare positions.
-template <int NMO, bool LR>
+template <int NMO, bool LR, int CAP>
 __device__ __forceinline__ void backflow_dets(const DevSystem &S, const Lane &L, double *wsm, const double *sPos,
                                               double x0, double x1, double x2, Core<NMO> &c);
 
@@ -769,7 +769,7 @@ __host__ __device__ inline int bf_pos_offset(const DevSystem &S);
 // of the AO evaluation and MF the MO contraction of pass 1 (FP64 when RT is
 // double).  FULLT: the full table layout (walker_lds<NMO, true>), which the
 // adjoint reads; otherwise the compact one.
-template <int NMO, typename RT, int MF = 0, bool EXPL = false, bool BF = false, bool PSI = false,
+template <int NMO, typename RT, int MF = 0, bool EXPL = false, int BF = 0, bool PSI = false,
           bool FULLT = false>
 __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, double *wsm, double &x0,
                                             double &x1, double &x2, Core<NMO> &c, void *stage = nullptr) {
@@ -818,7 +818,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     c.vpot = vpot;
 
     if constexpr (BF) {
-        backflow_dets<NMO, !EXPL>(S, L, wsm, sPos, x0, x1, x2, c);
+        backflow_dets<NMO, !EXPL, (BF == 1 ? kSmallCfgBF : kMaxCfgBF)>(S, L, wsm, sPos, x0, x1, x2, c);
         return;
     }
 
