@@ -660,7 +660,7 @@ def main():
     ap.add_argument("--summarize-trace", default=None,
                     help="print the dispatch statistics of --trace-kernel in this rocprofv3 "
                          "kernel-trace CSV (no GPU run)")
-    ap.add_argument("--trace-kernel", default=r"k_metropolis<20, double, 0, false, false>")
+    ap.add_argument("--trace-kernel", default=r"k_metropolis<20, double, 0, false, 0>")
     ap.add_argument("--trace-skip", type=int, default=0, help="leading dispatches to leave out")
     ap.add_argument("--trace-block", type=int, default=0,
                     help="dispatches per qmc_metropolis_block call (block spans; 0: none)")
