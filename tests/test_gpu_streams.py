@@ -91,3 +91,48 @@ def test_small_block_loop_equals_large_block(torch_cuda, qmc, prec, B):
     for k, (a, b) in enumerate(zip(A + [accA], P + [accP])):
         assert torch.equal(a[:B], b), k
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_host_threads_share_a_handle(torch_cuda, qmc, prec):
+    """Two host threads run 4-step blocks on one handle at once, each on its
+    own stream and walkers (both blocks use the handle's second stream); the
+    results equal the same blocks run one after the other."""
+    import threading
+    torch = torch_cuda
+    W = 32768 if prec == "fp64" else 65536
+    s, X0 = _co(torch, qmc, W, 24)
+    lp0, sg0, el0 = s.eval(X0, precision=prec)
+    torch.cuda.synchronize()
+    starts = [[t.clone() for t in (X0, lp0, sg0, el0)] for _ in range(2)]
+    seeds = (11, 12)
+    ref = []
+    for k in range(2):
+        st = [t.clone() for t in starts[k]]
+        acc = s.metropolis(*st, 4, 0.2, seeds[k], precision=prec)
+        ref.append(st + [acc])
+    torch.cuda.synchronize()
+    out = [None, None]
+    errors = []
+
+    def run(k):
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                st = [t.clone() for t in starts[k]]
+                acc = s.metropolis(*st, 4, 0.2, seeds[k], precision=prec)
+            stream.synchronize()
+            out[k] = st + [acc]
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=run, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        for a, b in zip(ref[k], out[k]):
+            assert torch.equal(a, b)
+    s.close()
