@@ -136,3 +136,27 @@ def test_two_host_threads_share_a_handle(torch_cuda, qmc, prec):
         for a, b in zip(ref[k], out[k]):
             assert torch.equal(a, b)
     s.close()
+
+
+def test_backflow_split_block_equals_batches(torch_cuda, qmc):
+    """Backflow blocks take the same two-stream split: CO with inverse
+    backflow (omega = 0.1), 8192 walkers (2048 waves, two halves) against
+    four single-stream batches of 2048 walkers, bit for bit."""
+    torch = torch_cuda
+    sysd = dict(synth.make_system("CO"))
+    sysd["bf_omega"] = 0.1
+    s = qmc.System(sysd)
+    W, B = 8192, 2048
+    X0 = torch.from_numpy(synth.init_walkers(sysd, W, 25)).cuda()
+    lp0, sg0, el0 = s.eval(X0)
+    A = [X0.clone(), lp0.clone(), sg0.clone(), el0.clone()]
+    accA = s.metropolis(*A, 2, 0.2, 99)
+    parts = []
+    for lo in range(0, W, B):
+        P = [t[lo:lo + B].clone() for t in (X0, lp0, sg0, el0)]
+        acc = s.metropolis(*P, 2, 0.2, 99, walker_offset=lo)
+        parts.append(P + [acc])
+    torch.cuda.synchronize()
+    for k in range(5):
+        assert torch.equal((A + [accA])[k], torch.cat([p[k] for p in parts])), k
+    s.close()
