@@ -192,10 +192,14 @@ qmc_status qmc_eval_psi_eloc(qmc_system *sys, int32_t precision, const double *d
    first call.  Results depend only on (seed, walker_offset + w, t), never on
    W or on how walkers are batched.  sigma must be finite (QMC_ENONFINITE)
    and >= 0 (QMC_EINVAL).  Enqueued as one kernel per step (the arrays carry
-   the state between them; a mixed form adds its re-evaluation kernels on
-   the handle's second stream), except QMC_FP64_EXPLICIT: one kernel.  An
-   FP64 block of at least 1536 waves of walkers runs its walkers in two
-   halves, one on `stream` and one on the second stream. */
+   the state between them; a mixed form adds its re-evaluation kernels, on
+   the handle's second stream for blocks of more than 8192 waves of walkers,
+   else on `stream`), except QMC_FP64_EXPLICIT and blocks of at most 1024
+   waves without backflow: one kernel with the step loop inside.  An FP64
+   block of at least 1536 waves runs its walkers in two halves, one on
+   `stream` and one on the second stream.  (A wave holds 64 / (2 G) walkers,
+   G the next power of two >= max(n_up, n_dn).)  The results do not depend
+   on these choices. */
 qmc_status qmc_metropolis_block(qmc_system *sys, int32_t precision, double *d_X, double *d_logpsi,
                                 double *d_sign, double *d_eloc, int64_t W, int32_t n_steps,
                                 double sigma, uint64_t seed, uint64_t step0,
