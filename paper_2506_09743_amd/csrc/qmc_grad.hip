@@ -52,10 +52,10 @@ struct GradOut {
 // of both.
 // After the MO-coefficient gradient the same block holds the walker's
 // positions [LW][3] and the Dual e-e-n tables of the Jastrow directions
-// (2 doubles per entry): [LW][n_atoms][2 een_n] factors, [LW][n_atoms][4]
+// (2 doubles per entry): [LW][n_atoms][2 een_n] factors, [LW][n_atoms][kEenGeo]
 // geometry.
 __host__ __device__ inline int grad_dual_size(const DevSystem &S) {
-    return 3 * S.LW + 2 * S.LW * S.n_atoms * (2 * S.een_n + 4);
+    return 3 * S.LW + 2 * S.LW * S.n_atoms * (2 * S.een_n + kEenGeo);
 }
 
 template <int NMO>
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kWave) void k_grad(DevSystem S, const double *__res
     {
         double *sP = wsm;                                   // [LW][3]
         Dual *dF = (Dual *)(wsm + 3 * S.LW);                // [LW][n_atoms][2 een_n]
-        Dual *dG = dF + S.LW * S.n_atoms * 2 * S.een_n;     // [LW][n_atoms][4]
+        Dual *dG = dF + S.LW * S.n_atoms * 2 * S.een_n;     // [LW][n_atoms][kEenGeo]
         sP[3 * L.lw + 0] = x0;
         sP[3 * L.lw + 1] = x1;
         sP[3 * L.lw + 2] = x2;

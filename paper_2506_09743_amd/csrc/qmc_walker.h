@@ -496,8 +496,12 @@ __device__ __forceinline__ void mo_values_mfma(const DevSystem &S, int lane, voi
 // same space holds the e-e-n factor table (een_table doubles at 0, when
 // e-e-n terms exist) and the positions [LW][3] + pivot rows [2][NMO] at
 // pos_offset.
+// Doubles of e-e-n geometry per lane and nucleus: r, the unit vector from
+// the nucleus, 1 / r.
+constexpr int kEenGeo = 5;
+
 __host__ __device__ inline int een_table(const DevSystem &S) {
-    return S.een_n > 0 ? S.LW * S.n_atoms * (2 * S.een_n + 4) : 0;
+    return S.een_n > 0 ? S.LW * S.n_atoms * (2 * S.een_n + kEenGeo) : 0;
 }
 
 template <int NMO, bool FULL = true>
@@ -607,8 +611,8 @@ struct SeedPrm {
 };
 
 // The lane's e-e-n factor table: per nucleus a, [een_n][2] factor values
-// f(a1, b1; u) and f(a2, b2; u) of its electron at u = r_a e, then [4] the
-// geometry (u and the unit vector from the nucleus).  T values, LDS.
+// f(a1, b1; u) and f(a2, b2; u) of its electron at u = r_a e, then [kEenGeo] the
+// geometry (u, the unit vector from the nucleus, 1 / u).  T values, LDS.
 template <typename T, typename Prm>
 __device__ __forceinline__ void een_table_fill(const DevSystem &S, const Lane &L, double x0, double x1, double x2,
                                                T *sF, T *sG, const Prm &prm) {
@@ -617,11 +621,12 @@ __device__ __forceinline__ void een_table_fill(const DevSystem &S, const Lane &L
         const T e0 = x0 - prm.R(a, 0), e1 = x1 - prm.R(a, 1), e2 = x2 - prm.R(a, 2);
         const T u = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
         const T ui = 1.0 / u;
-        T *g = sG + (L.lw * S.n_atoms + a) * 4;
+        T *g = sG + (L.lw * S.n_atoms + a) * kEenGeo;
         g[0] = u;
         g[1] = e0 * ui;
         g[2] = e1 * ui;
         g[3] = e2 * ui;
+        g[4] = ui;
         T *f = sF + (L.lw * S.n_atoms + a) * 2 * S.een_n;
         for (int m = 0; m < S.een_n; ++m) {
             f[2 * m] = prm.een(m, 1) * u * rcp_ge1(1.0 + prm.een(m, 2) * u);
@@ -717,7 +722,7 @@ __device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const L
             const T cm = prm.een(m, 0);
             for (int a = 0; a < S.n_atoms; ++a) {
                 if (!prm.use_een(m, a)) continue;
-                const T *g = sG + (L.lw * S.n_atoms + a) * 4;
+                const T *g = sG + (L.lw * S.n_atoms + a) * kEenGeo;
                 const T u = g[0];
                 const T qo = rcp_ge1(1.0 + bo * u);
                 const T fo = ao * u * qo, fo1 = ao * qo * qo, fo2 = -2.0 * bo * fo1 * qo;
@@ -727,7 +732,7 @@ __device__ __forceinline__ JasTerms<T> jastrow_terms(const DevSystem &S, const L
                 o.g0 += cp * (fo1 * f3 * g[1] + fo * f31 * w0);
                 o.g1 += cp * (fo1 * f3 * g[2] + fo * f31 * w1);
                 o.g2 += cp * (fo1 * f3 * g[3] + fo * f31 * w2);
-                o.lap += cp * ((fo2 + 2.0 * fo1 / u) * f3 + 2.0 * fo1 * f31 * uw + fo * (f32 + 2.0 * f31 * rinv));
+                o.lap += cp * ((fo2 + 2.0 * fo1 * g[4]) * f3 + 2.0 * fo1 * f31 * uw + fo * (f32 + 2.0 * f31 * rinv));
             }
         }
     }
@@ -786,7 +791,7 @@ __device__ __forceinline__ void core_stages(const DevSystem &S, const Lane &L, d
     double *sPos = wsm + (BF ? bf_pos_offset<NMO, !EXPL>(S) : pos_offset<NMO, kFull>(S));
     double *sPiv = sPos + 3 * S.LW;          // [2][NMO] during it
     // e-e-n table before the elimination: per lane [n_atoms][een_n][2]
-    // factor values (f1, f2) of its electron, then [n_atoms][4] geometry
+    // factor values (f1, f2) of its electron, then [n_atoms][kEenGeo] geometry
     // (r, unit vector from the nucleus)
     double *sF = wsm;
     double *sG = wsm + S.LW * S.n_atoms * 2 * S.een_n;
